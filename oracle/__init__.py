@@ -1,0 +1,236 @@
+"""CPU FP64 oracle for the StePS direct-summation path.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product library never imports,
+links or runs anything here, and this package imports nothing from it.
+
+``oracle.c`` holds the arithmetic (plain C, FP64, Neumaier sums, OpenMP over
+i); this module compiles it with gcc on first use (or when the source is newer
+than the library) and wraps it with ctypes.  Every function states the passage
+of Racz et al. (2018) it follows:
+
+* :func:`kernel_F`, :func:`kernel_phi` -- spline-softened force kernel,
+  Sec. 2.2 Eq. 4; its potential (derived: the paper gives only the force).
+* :func:`forces` -- G-free pair sum S_i of Sec. 2.2 Eq. 8 with Eq. 3.
+* :func:`potential` -- G-free softened potential (diagnostic).
+* :func:`hubble`, :func:`dt` -- Sec. 2.2 Eq. 1; exact dt for a step in a
+  (Sec. 2.3, the interval Eq. 13 approximates to first order).
+* :func:`kdk_step` -- Sec. 2.3 Eqs. 9-11 with the acceleration of Eq. 8.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+           "-fopenmp", "-fPIC", "-shared"]
+
+
+def build(force: bool = False) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` with gcc; returns its path."""
+    stale = (not os.path.exists(_LIB) or
+             os.path.getmtime(_LIB) < os.path.getmtime(_SRC))
+    if force or stale:
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", *_CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        d, i64, i32 = ctypes.c_double, ctypes.c_int64, ctypes.c_int
+        vp = ctypes.c_void_p
+        lib.oracle_kernel_F.argtypes = [d, d]
+        lib.oracle_kernel_F.restype = d
+        lib.oracle_kernel_phi.argtypes = [d, d]
+        lib.oracle_kernel_phi.restype = d
+        lib.oracle_forces.argtypes = [i64, vp, vp, vp, i64, vp, vp, vp, i32]
+        lib.oracle_forces.restype = i32
+        lib.oracle_potential.argtypes = [i64, vp, vp, vp, i64, vp, vp, i32]
+        lib.oracle_potential.restype = i32
+        lib.oracle_hubble.argtypes = [d, ctypes.POINTER(_Cosmo)]
+        lib.oracle_hubble.restype = d
+        lib.oracle_dt.argtypes = [d, d, ctypes.POINTER(_Cosmo)]
+        lib.oracle_dt.restype = d
+        lib.oracle_kdk_step.argtypes = [i64, vp, vp, vp, vp, vp, d, d,
+                                        ctypes.POINTER(_Cosmo), i32]
+        lib.oracle_kdk_step.restype = i32
+        lib.oracle_G.argtypes = []
+        lib.oracle_G.restype = d
+        lib.oracle_kms_to_mpc_per_gyr.argtypes = []
+        lib.oracle_kms_to_mpc_per_gyr.restype = d
+        lib.oracle_num_threads.argtypes = []
+        lib.oracle_num_threads.restype = i32
+        _lib = lib
+    return _lib
+
+
+class _Cosmo(ctypes.Structure):
+    _fields_ = [("H0", ctypes.c_double), ("omega_m", ctypes.c_double),
+                ("omega_l", ctypes.c_double), ("omega_r", ctypes.c_double),
+                ("omega_k", ctypes.c_double), ("G", ctypes.c_double),
+                ("newtonian_test", ctypes.c_int)]
+
+
+@dataclass
+class Cosmology:
+    """Background parameters (Sec. 2.2 Eq. 1).  H0 in km/s/Mpc; omega_k None
+    means 1 - omega_m - omega_l - omega_r; G None means the oracle's value
+    in Mpc^3 / (Msun Gyr^2)."""
+    H0: float = 70.0
+    omega_m: float = 0.3
+    omega_l: float = 0.7
+    omega_r: float = 0.0
+    omega_k: float | None = None
+    G: float | None = None
+    newtonian_test: bool = False
+
+    def _c(self) -> _Cosmo:
+        ok = self.omega_k
+        if ok is None or (isinstance(ok, float) and math.isnan(ok)):
+            ok = 1.0 - self.omega_m - self.omega_l - self.omega_r
+        g = G() if self.G is None else self.G
+        return _Cosmo(self.H0, self.omega_m, self.omega_l, self.omega_r, ok,
+                      g, 1 if self.newtonian_test else 0)
+
+
+def G() -> float:
+    """Newton's constant in Mpc^3 / (Msun Gyr^2)."""
+    return _load().oracle_G()
+
+
+def kms_to_mpc_per_gyr() -> float:
+    return _load().oracle_kms_to_mpc_per_gyr()
+
+
+def num_threads() -> int:
+    return _load().oracle_num_threads()
+
+
+def kernel_F(r: float, h: float) -> float:
+    """F(r, h) of Eq. 4 (G-free force magnitude per unit source mass)."""
+    return _load().oracle_kernel_F(float(r), float(h))
+
+
+def kernel_phi(r: float, h: float) -> float:
+    """Potential whose radial derivative is F(r, h); -1/r beyond h."""
+    return _load().oracle_kernel_phi(float(r), float(h))
+
+
+def _soa(a, n):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape == (n, 3) and n != 3:
+        a = np.ascontiguousarray(a.T)
+    if a.shape != (3, n):
+        raise ValueError("expected a (3, n) or (n, 3) array, got %r" % (a.shape,))
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def forces(pos, mass, soft, idx=None, want_kappa=False, nthreads=0):
+    """G-free pair sum S (Eq. 8) for all i, or for the rows listed in idx.
+
+    pos: (3, n) SoA (an (n, 3) array is transposed).  Returns S as (3, ni),
+    plus kappa (ni,) when want_kappa.
+    """
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    n = mass.shape[0]
+    pos = _soa(pos, n)
+    soft = np.ascontiguousarray(soft, dtype=np.float64)
+    if soft.shape != (n,):
+        raise ValueError("soft must have shape (n,)")
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        if idx.size and (idx.min() < 0 or idx.max() >= n):
+            raise ValueError("idx out of range")
+        ni = idx.shape[0]
+    else:
+        ni = n
+    acc = np.zeros((3, ni), dtype=np.float64)
+    kap = np.zeros(ni, dtype=np.float64) if want_kappa else None
+    rc = _load().oracle_forces(n, _ptr(pos), _ptr(mass), _ptr(soft), ni,
+                               _ptr(idx), _ptr(acc), _ptr(kap), int(nthreads))
+    if rc:
+        raise ValueError("oracle_forces: bad argument")
+    return (acc, kap) if want_kappa else acc
+
+
+def potential(pos, mass, soft, idx=None, nthreads=0):
+    """G-free softened potential Phi_i = sum_j m_j phi(r_ij, h_i + h_j)."""
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    n = mass.shape[0]
+    pos = _soa(pos, n)
+    soft = np.ascontiguousarray(soft, dtype=np.float64)
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        ni = idx.shape[0]
+    else:
+        ni = n
+    phi = np.zeros(ni, dtype=np.float64)
+    rc = _load().oracle_potential(n, _ptr(pos), _ptr(mass), _ptr(soft), ni,
+                                  _ptr(idx), _ptr(phi), int(nthreads))
+    if rc:
+        raise ValueError("oracle_potential: bad argument")
+    return phi
+
+
+def hubble(a: float, cosmo: Cosmology) -> float:
+    """H(a) in 1/Gyr (Eq. 1)."""
+    c = cosmo._c()
+    return _load().oracle_hubble(float(a), ctypes.byref(c))
+
+
+def dt(a: float, da: float, cosmo: Cosmology) -> float:
+    """Cosmic time (Gyr) for the scale factor to go from a to a + da."""
+    c = cosmo._c()
+    return _load().oracle_dt(float(a), float(da), ctypes.byref(c))
+
+
+def kdk_step(pos, vel, mass, soft, S, a, da, cosmo: Cosmology, nthreads=0):
+    """One KDK step (Eq. 11) in place on SoA float64 arrays pos, vel, S."""
+    n = mass.shape[0]
+    for arr in (pos, vel, S):
+        if arr.shape != (3, n) or arr.dtype != np.float64 or \
+                not arr.flags.c_contiguous:
+            raise ValueError("pos, vel, S must be C-contiguous float64 (3, n)")
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    soft = np.ascontiguousarray(soft, dtype=np.float64)
+    c = cosmo._c()
+    rc = _load().oracle_kdk_step(n, _ptr(pos), _ptr(vel), _ptr(mass),
+                                 _ptr(soft), _ptr(S), float(a), float(da),
+                                 ctypes.byref(c), int(nthreads))
+    if rc:
+        raise ValueError("oracle_kdk_step: bad argument")
+
+
+def run(pos, vel, mass, soft, a_grid, cosmo: Cosmology, nthreads=0):
+    """Integrate over the scale-factor grid a_grid (KDK per interval).
+
+    Copies its inputs; returns (pos, vel, S) at a_grid[-1].
+    """
+    n = mass.shape[0]
+    pos = _soa(pos, n).copy()
+    vel = _soa(vel, n).copy()
+    S = forces(pos, mass, soft, nthreads=nthreads)
+    for k in range(len(a_grid) - 1):
+        kdk_step(pos, vel, mass, soft, S, a_grid[k],
+                 a_grid[k + 1] - a_grid[k], cosmo, nthreads)
+    return pos, vel, S
