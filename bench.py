@@ -1,0 +1,225 @@
+"""Benchmark of the StePS direct-summation hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2]
+                    [--no-cpu-baseline] [--no-modes]
+
+A step is one comoving KDK step (kick + drift, one O(N^2) pair sum, kick) of
+the whole particle set, with state resident in HBM.  Default workload:
+N = 2^18 stereographically projected particles, D = 200 Mpc,
+r_max = 2000 Mpc, LCDM (0.3089 / 0.6911 / 67.74), FP64, stepping along its
+200-step log-uniform grid from a = 0.02.  The value is ordered pair
+interactions per second over the timed steps (N^2 per step).
+
+Also reported on the same JSON line:
+  roofline     -- force kernel: 20 flop per ordered pair (convention) over
+                  its average launch time (HIP events on its own stream),
+                  against the FP64 vector peak 78.6 TFLOP/s ("bound": "alu");
+  cpu_baseline -- the CPU FP64 oracle on a bounded seeded sample of i rows
+                  against all N j (rank 0 only);
+  modes        -- force-kernel pair rate in FP64 and both mixed modes at the
+                  same N and at N = 2^21, with the relative force error
+                  against the oracle sample (median, max).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_PEAK_TF = 78.6
+FP32_PEAK_TF = 157.3
+FLOP_PER_PAIR = 20
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 5])
+    ap.add_argument("--precision", default="fp64",
+                    choices=["fp64", "mixed", "kahan"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU "
+              "path (each GPU would own a block of i-rows and all-gather "
+              "positions once per step; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1811_05903_amd as st
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+    ps = synth.config(args.workload)
+    n = ps.n
+    log("workload %d: n=%d precision=%s" % (args.workload, n, args.precision))
+    grid = ps.a_grid()
+    c = ps.cosmo
+    cosmo = st.Cosmology(c.H0, c.omega_m, c.omega_l, c.omega_r)
+    stream = torch.cuda.current_stream()
+    ctx = st.Context(0, precision=args.precision, flags=st.STEPS_PROFILE,
+                     stream=stream)
+    pos, vel, mass, soft = dev(ps.pos), dev(ps.vel), dev(ps.mass), dev(ps.soft)
+    acc = st.steps_forces(pos, mass, soft, ctx=ctx)
+
+    total = args.warmup + args.steps
+    if total > len(grid) - 1:
+        raise SystemExit("at most %d steps on this grid" % (len(grid) - 1))
+    k = 0
+    for _ in range(args.warmup):
+        st.steps_step(pos, vel, mass, soft, acc, grid[k], grid[k + 1] - grid[k],
+                      cosmo, ctx=ctx)
+        k += 1
+    torch.cuda.synchronize()
+    ctx.force_timing(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st.steps_step(pos, vel, mass, soft, acc, grid[k], grid[k + 1] - grid[k],
+                      cosmo, ctx=ctx)
+        k += 1
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    force_ms, force_cnt = ctx.force_timing(reset=True)
+    elapsed = t1 - t0
+    ms_step = 1e3 * elapsed / args.steps
+    pairs = float(n) * n
+    value = pairs * args.steps / elapsed
+    kern_ms = force_ms / max(1, force_cnt)
+    achieved = FLOP_PER_PAIR * pairs / (kern_ms * 1e-3) / 1e12
+    peak = FP64_PEAK_TF if args.precision == "fp64" else FP32_PEAK_TF
+    tile = ctx.get_tile(n)
+    log("%d steps: %.2f ms/step, %.3e pairs/s; force kernel %.2f ms (%d launches)"
+        % (args.steps, ms_step, value, kern_ms, force_cnt))
+    assert bool(torch.isfinite(pos).all()) and bool(torch.isfinite(acc).all())
+
+    out = {
+        "metric": "pair interactions/s (ordered pairs, whole KDK step)",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32-pair/f64-acc",
+        "data": "synthetic",
+        "config": {"workload": "stereographic sphere N=%d D=%g r_max=%g, %s, "
+                               "KDK from a=%.3f" % (n, ps.params["D"],
+                                                    ps.params["r_max"],
+                                                    args.precision, grid[0]),
+                   "n": n, "precision": args.precision, "tile": tile,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None,
+                     "kernel": "k_force_%s" % ("f64" if args.precision == "fp64" else "mixed"),
+                     "kernel_ms": kern_ms,
+                     "flop_per_pair": FLOP_PER_PAIR},
+    }
+
+    sample_rows = None
+    if not args.no_cpu_baseline:
+        import oracle
+        rng = np.random.default_rng(12345)
+        probe = rng.choice(n, 64, replace=False)
+        t = time.perf_counter()
+        oracle.forces(ps.pos, ps.mass, ps.soft, idx=probe)
+        rate = 64 * n / (time.perf_counter() - t)
+        m = int(min(n, max(64, rate * args.cpu_seconds / n)))
+        idx = np.sort(rng.choice(n, m, replace=False))
+        log("cpu baseline: oracle on %d sampled rows (%d threads)" % (m, oracle.num_threads()))
+        # the same positions the GPU starts from (before stepping)
+        t = time.perf_counter()
+        ref = oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx)
+        dt = time.perf_counter() - t
+        sample_rows = (idx, ref)
+        out["cpu_baseline"] = {
+            "value": m * float(n) / dt, "unit": "pairs/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "FP64 oracle pair sums for %d seeded-sampled i of the "
+                      "N=%d set against all j (%.1f s)" % (m, n, dt)}
+
+    if not args.no_modes:
+        out["modes"] = mode_table(st, ps, sample_rows, dev)
+        big = synth.config(3)
+        big_rows = None
+        if not args.no_cpu_baseline:
+            import oracle
+            bidx = np.sort(np.random.default_rng(3).choice(big.n, 32, replace=False))
+            big_rows = (bidx, oracle.forces(big.pos, big.mass, big.soft, idx=bidx))
+        out["modes_n2e21"] = mode_table(st, big, big_rows, dev)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def mode_table(st, ps, rows, dev):
+    """Force-kernel rate per precision mode at this N, one timed launch after
+    one warm-up, and the error against the oracle rows if given."""
+    import numpy as np
+    import torch
+    n = ps.n
+    pos, mass, soft = dev(ps.pos), dev(ps.mass), dev(ps.soft)
+    res = {}
+    for prec in ("fp64", "mixed", "kahan"):
+        ctx = st.Context(0, precision=prec, flags=st.STEPS_PROFILE)
+        acc = st.steps_forces(pos, mass, soft, ctx=ctx)
+        torch.cuda.synchronize()
+        ctx.force_timing(reset=True)
+        reps = 3 if n <= 300000 else 1
+        for _ in range(reps):
+            st.steps_forces(pos, mass, soft, acc=acc, ctx=ctx)
+        ms, cnt = ctx.force_timing(reset=True)
+        kms = ms / cnt
+        rate = float(n) * n / (kms * 1e-3)
+        peak = FP64_PEAK_TF if prec == "fp64" else FP32_PEAK_TF
+        entry = {"kernel_ms": kms, "pairs_per_s": rate,
+                 "tflops_20": FLOP_PER_PAIR * rate / 1e12,
+                 "frac_peak": FLOP_PER_PAIR * rate / 1e12 / peak,
+                 "tile": ctx.get_tile(n)}
+        if rows is not None:
+            idx, ref = rows
+            got = acc.cpu().numpy()[:, idx]
+            err = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+            entry["rel_err_median"] = float(np.median(err))
+            entry["rel_err_max"] = float(err.max())
+            entry["rel_err_rows"] = int(idx.size)
+        res[prec] = entry
+        log("n=%d %s: %.2f ms, %.3e pairs/s%s" % (
+            n, prec, kms, rate,
+            "" if rows is None else ", err median %.2e max %.2e" % (
+                entry["rel_err_median"], entry["rel_err_max"])))
+        ctx.close()
+    res["mixed_speedup_vs_fp64"] = res["mixed"]["pairs_per_s"] / res["fp64"]["pairs_per_s"]
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * steps.h -- C ABI of libsteps, an MI355X (gfx950) implementation of the
+ * direct-summation hot path of StePS (Racz, Szapudi, Dobos, Csabai, Szalay
+ * 2018, "StePS: A Multi-GPU Cosmological N-body Code for Compactified
+ * Simulations"): the O(N^2) spline-softened pair sum over a compactified
+ * spherical particle set with per-particle mass and softening, and the
+ * comoving kick-drift-kick leapfrog that consumes it.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: Mpc, Gyr, solar masses; velocities in Mpc/Gyr; H0 in km/s/Mpc.
+ *
+ * Pointers: every array argument is a DEVICE pointer on the context's
+ * device (hipMalloc'd memory, or a torch tensor's data_ptr()).  Arrays are
+ * structure-of-arrays, 8-byte (double) elements, contiguous:
+ *   pos, vel, acc : [3][n]  (all x, then all y, then all z)
+ *   mass, soft    : [n]
+ * Output arrays must not overlap any input array.
+ *
+ * Ownership: the caller owns every array.  The library never frees a caller
+ * pointer and keeps none of them past the call.  The context owns only its
+ * scratch memory (partial sums, FP32 shadow copies), allocated on demand and
+ * freed by steps_ctx_destroy.
+ *
+ * Asynchrony: compute calls enqueue work on the context's stream and return
+ * without waiting.  Argument errors are reported by the return code before
+ * anything is enqueued, and then nothing has been written.  Errors raised by
+ * the device while the work runs surface at steps_sync (or at the next call
+ * on that context).
+ *
+ * Return codes: STEPS_OK, or one of the negative STEPS_E_* values below.
+ * steps_last_error() returns a message for the last failure on the calling
+ * thread.  No C++ exception and no abort crosses this interface.
+ *
+ * The pair sum S returned by the force calls is G-free:
+ *   S_i = sum_{j != i, r_ij > 0} m_j F(r_ij, h_i + h_j) (x_j - x_i) / r_ij
+ * with F the spline-softened kernel of Sec. 2.2 Eq. 4 (support radius
+ * h = h_i + h_j, Eqs. 2 and 8; F = 1/r^2 for r >= h).  The comoving pair
+ * acceleration of Eq. 8 is G S_i / a^3; pass G*m as mass to get physical
+ * units directly.  Pairs at zero separation contribute nothing.
+ */
+#ifndef STEPS_H
+#define STEPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ----------------------------------------------------- */
+#define STEPS_OK 0
+#define STEPS_E_INVAL (-1)       /* bad argument (null pointer, n < 0, ...) */
+#define STEPS_E_NOMEM (-2)       /* device scratch allocation failed */
+#define STEPS_E_HIP (-3)         /* HIP runtime error; message has the text */
+#define STEPS_E_NONFINITE (-4)   /* non-finite input (STEPS_CHECK_FINITE) */
+#define STEPS_E_UNSUPPORTED (-5) /* option not available in this build */
+
+/* ---- precision modes (steps_ctx_set_precision) ------------------------ */
+/* FP64 throughout; deterministic (fixed summation order, no atomics). */
+#define STEPS_FP64 0
+/* Pair arithmetic in FP32 on an FP32 copy of the inputs; each j-tile's FP32
+ * partial sum is added into an FP64 accumulator. */
+#define STEPS_MIXED_F64ACC 1
+/* As STEPS_MIXED_F64ACC, but tile partials are added into a Kahan-
+ * compensated FP32 (sum, compensation) pair. */
+#define STEPS_MIXED_KAHAN 2
+
+/* ---- context flags (steps_ctx_set_flags) ------------------------------ */
+/* Check pos/vel/mass/soft for NaN/Inf on every compute call (O(N), waits
+ * for the device); a non-finite value gives STEPS_E_NONFINITE and nothing
+ * else runs. */
+#define STEPS_CHECK_FINITE 1u
+/* Time every force-kernel launch with HIP events on the context stream;
+ * read the totals with steps_ctx_force_timing. */
+#define STEPS_PROFILE 2u
+
+/* ---- cosmology modes -------------------------------------------------- */
+/* Comoving spherical equations of motion, Sec. 2.2 Eq. 8. */
+#define STEPS_COMOVING_SPHERICAL 0
+/* Plain Newtonian test mode: a == 1, H == 0, no radial term, the step
+ * variable is time itself (dt = da).  For integrator tests only. */
+#define STEPS_NEWTONIAN_TEST 1
+
+/* Background cosmology (Sec. 2.2 Eq. 1). */
+typedef struct steps_cosmology {
+  double H0;      /* Hubble constant, km/s/Mpc (> 0 in comoving mode) */
+  double omega_m; /* matter density parameter */
+  double omega_l; /* dark-energy density parameter */
+  double omega_r; /* radiation density parameter */
+  double omega_k; /* curvature; NaN means 1 - omega_m - omega_l - omega_r */
+  double G;       /* Newton's constant in Mpc^3/(Msun Gyr^2); 0 = built-in */
+  int32_t mode;   /* STEPS_COMOVING_SPHERICAL or STEPS_NEWTONIAN_TEST */
+  int32_t reserved; /* must be 0 */
+} steps_cosmology;
+
+/* Launch shape of the force kernels.  r: i-particles held per lane;
+ * tj: j-particles per LDS tile; jsplit: number of j-ranges the sum is split
+ * into (partials reduced in fixed order); variant: kernel option -- for
+ * STEPS_FP64, 0 evaluates r^-3 from v_rsq_f64 with a second-order
+ * correction, 1 with a first-order one (one instruction less per pair,
+ * ~1e-15 typical extra relative error); mixed modes accept only 0. */
+typedef struct steps_tile {
+  int32_t r;
+  int32_t tj;
+  int32_t jsplit;
+  int32_t variant;
+} steps_tile;
+
+typedef struct steps_ctx steps_ctx;
+
+/* ---- version and errors ----------------------------------------------- */
+const char *steps_version(void);
+/* Message for the last failing call on this thread ("" if none).  The
+ * pointer stays valid until the next call on this thread. */
+const char *steps_last_error(void);
+
+/* ---- context ---------------------------------------------------------- */
+/* Create a context on HIP device `device`: null stream, STEPS_FP64, no
+ * flags, tile chosen by the built-in heuristic.  *out receives the handle. */
+int steps_ctx_create(int device, steps_ctx **out);
+/* Wait for the context's work, free its scratch and the handle.  NULL is a
+ * no-op. */
+int steps_ctx_destroy(steps_ctx *ctx);
+/* Enqueue subsequent work on `stream` (a hipStream_t on the context's
+ * device; NULL = the null stream).  The caller keeps the stream alive. */
+int steps_ctx_set_stream(steps_ctx *ctx, void *stream);
+int steps_ctx_set_precision(steps_ctx *ctx, int precision);
+int steps_ctx_set_flags(steps_ctx *ctx, uint32_t flags);
+/* Force a launch shape (validated against the compiled variants; r and tj
+ * must name one of them, jsplit >= 1).  Passing NULL returns to automatic
+ * selection (tuned table, else heuristic). */
+int steps_ctx_set_tile(steps_ctx *ctx, const steps_tile *tile);
+/* The shape the context would use for n particles in its precision. */
+int steps_ctx_get_tile(steps_ctx *ctx, int64_t n, steps_tile *out);
+/* Wait until all work enqueued on the context has finished; reports device
+ * errors raised by that work. */
+int steps_sync(steps_ctx *ctx);
+/* With STEPS_PROFILE: total milliseconds and number of force-kernel
+ * launches timed since the last reset (waits for the stream).  reset != 0
+ * clears the totals after reading. */
+int steps_ctx_force_timing(steps_ctx *ctx, double *total_ms, int64_t *count,
+                           int reset);
+
+/* ---- forces: Sec. 2.2 Eq. 8 (pair term) with Eqs. 3-4 ------------------ */
+/* acc <- S (G-free pair sum, see top of file) for all n particles.
+ * pos [3][n], mass [n], soft [n] (softening lengths h_i >= 0, the support
+ * radius of particle i's share of the kernel), acc [3][n] output.
+ * n == 0 is a no-op; n == 1 gives acc = 0.  n must be <= 2^30. */
+int steps_forces_ctx(steps_ctx *ctx, const double *pos, const double *mass,
+                     const double *soft, int64_t n, double *acc);
+/* Same on the default context of the calling thread's current device
+ * (null stream, STEPS_FP64). */
+int steps_forces(const double *pos, const double *mass, const double *soft,
+                 int64_t n, double *acc);
+
+/* ---- softened potential (diagnostic) ---------------------------------- */
+/* phi_i <- sum_{j != i, r_ij > 0} m_j phi(r_ij, h_i + h_j), G-free, with
+ * phi the potential of the Eq. 4 kernel (phi = -1/r for r >= h,
+ * d phi/dr = F).  Always FP64.  phi [n] output. */
+int steps_potential_ctx(steps_ctx *ctx, const double *pos, const double *mass,
+                        const double *soft, int64_t n, double *phi);
+int steps_potential(const double *pos, const double *mass, const double *soft,
+                    int64_t n, double *phi);
+
+/* ---- one KDK step: Sec. 2.3 Eqs. 9-11 with the acceleration of Eq. 8 --- */
+/* Advance pos, vel from scale factor a to a + da (in STEPS_NEWTONIAN_TEST
+ * mode: from time a to a + da) with U = K(dt/2) D(dt) K(dt/2), where
+ *   dt = integral_a^{a+da} da' / (a' H(a'))   (exact; Eq. 1)
+ *   A  = G S / a^3 + (Omega_m H0^2 / 2) x / a^3 - 2 H(a) v     (Eq. 8)
+ * The radial term uses the physical mean density Omega_m rho_crit / a^3.
+ * The first half-kick evaluates A at (x_n, v_n, a_n); the second at
+ * (x_{n+1}, v_{n+1}, a_{n+1}), solved in closed form since A is linear in v
+ * (this keeps the step second order and time reversible).
+ * On entry acc must hold S(pos) (call steps_forces once before the first
+ * step); on exit pos, vel and acc = S(new pos) are updated.  Exactly one
+ * O(N^2) evaluation per step, in the context's precision; kick and drift
+ * are always FP64.  da may be negative if a + da > 0.
+ * Errors (nothing written): STEPS_E_INVAL for null pointers, n < 0,
+ * non-finite a or da, a <= 0 or a + da <= 0 in comoving mode, H0 <= 0,
+ * G < 0, reserved != 0, an unknown mode, or H(a)^2 <= 0 anywhere on
+ * [a, a + da]. */
+int steps_step_ctx(steps_ctx *ctx, double *pos, double *vel,
+                   const double *mass, const double *soft, int64_t n,
+                   double *acc, double a, double da,
+                   const steps_cosmology *cosmo);
+int steps_step(double *pos, double *vel, const double *mass,
+               const double *soft, int64_t n, double *acc, double a,
+               double da, const steps_cosmology *cosmo);
+
+/* ---- background helpers (host only, no device work) ------------------- */
+/* H(a) in 1/Gyr (Eq. 1). */
+int steps_hubble(const steps_cosmology *cosmo, double a, double *out);
+/* dt (Gyr) for the scale factor to go from a to a + da. */
+int steps_dt(const steps_cosmology *cosmo, double a, double da, double *out);
+/* Built-in G in Mpc^3/(Msun Gyr^2) and km/s in Mpc/Gyr. */
+double steps_G(void);
+double steps_kms_to_mpc_per_gyr(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STEPS_H */

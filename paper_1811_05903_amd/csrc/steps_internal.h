@@ -1,0 +1,73 @@
+// Internal interface between the host runtime and the gfx950 kernels of
+// libsteps.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace steps {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
+
+enum PrecClass { kClassF64 = 0, kClassMixed = 1 };
+
+// Arguments of one force-kernel launch.  pos/mass/soft point at double
+// arrays (kClassF64) or at the FP32 shadow (kClassMixed): x,y,z,m,h as
+// five [n] float arrays starting at `shadow`.
+struct ForceLaunch {
+  const double *pos = nullptr;
+  const double *mass = nullptr;
+  const double *soft = nullptr;
+  const float *shadow = nullptr;
+  int n = 0;
+  int jchunk = 0;   // j-range per grid row (multiple of the tile size)
+  int jsplit = 1;   // grid rows; > 1 writes partials
+  double *out = nullptr;       // [jsplit][3][n] (or acc when jsplit == 1)
+  int kahan = 0;               // mixed only: Kahan FP32 accumulation
+};
+
+struct ForceVariant {
+  int cls;   // PrecClass
+  int r;     // i-particles per lane
+  int tj;    // j-particles per LDS tile
+  int variant;  // kernel-specific option (FP64: 0 with e^2 term, 1 without)
+  hipError_t (*launch)(const ForceLaunch &, hipStream_t);
+};
+
+// All compiled force-kernel variants.
+const ForceVariant *force_variants(int *count);
+const ForceVariant *find_force_variant(int cls, int r, int tj, int variant);
+
+// Sum jsplit partials [jsplit][3][n] into acc [3][n] in fixed order.
+hipError_t launch_reduce_partials(const double *part, int jsplit, int n,
+                                  double *acc, hipStream_t s);
+
+// Softened potential (FP64), same partial layout with 1 component.
+hipError_t launch_potential(const double *pos, const double *mass,
+                            const double *soft, int n, int jchunk, int jsplit,
+                            double *out, hipStream_t s);
+hipError_t launch_reduce_partials1(const double *part, int jsplit, int n,
+                                   double *phi, hipStream_t s);
+
+// FP32 shadow [5][n] (x, y, z, m, h) from the FP64 inputs.
+hipError_t launch_shadow(const double *pos, const double *mass,
+                         const double *soft, int n, float *shadow,
+                         hipStream_t s);
+
+// First half-kick then drift, Eqs. 9-10:
+//   v <- v + hdt (gA S + radA x - drag v);  x <- x + dt v
+hipError_t launch_kick_drift(double *pos, double *vel, const double *S, int n,
+                             double hdt, double gA, double radA, double drag,
+                             double dt, hipStream_t s);
+// Second half-kick with the drag at the end-of-step velocity:
+//   v <- (v + hdt (gA S + radA x)) * inv,  inv = 1 / (1 + drag hdt)
+hipError_t launch_kick_end(const double *pos, double *vel, const double *S,
+                           int n, double hdt, double gA, double radA,
+                           double inv, hipStream_t s);
+
+// Sets *flag (device int, must start at 0) to 1 if any of the count doubles
+// at p is NaN or Inf.
+hipError_t launch_check_finite(const double *p, int64_t count, int *flag,
+                               hipStream_t s);
+
+}  // namespace steps

@@ -1,0 +1,139 @@
+"""Argument errors through the C ABI on a GPU host.  Every bad call must be
+rejected on the host, before any kernel is enqueued, and write nothing.
+Each case leaves a NULL pointer later in the argument list as a backstop,
+so a validation bug shows up as the wrong message, never as a launch."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+VP = ctypes.c_void_p
+
+
+@pytest.fixture(scope="module")
+def st():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1811_05903_amd as m
+    m.load()
+    return m
+
+
+def _p(t):
+    return VP(t.data_ptr())
+
+
+def _msg(lib):
+    return lib.steps_last_error().decode()
+
+
+def test_negative_and_huge_n(st):
+    lib = st.load()
+    assert lib.steps_forces(None, None, None, -1, None) == st.STEPS_E_INVAL
+    assert lib.steps_forces(None, None, None, (1 << 30) + 1, None) == st.STEPS_E_INVAL
+    assert "2^30" in _msg(lib)
+
+
+def test_host_pointer_rejected(st):
+    lib = st.load()
+    host_arr = np.zeros(3 * 64)
+    rc = lib.steps_forces(VP(host_arr.ctypes.data), None, None, 64, None)
+    assert rc == st.STEPS_E_INVAL
+    assert "pos" in _msg(lib)
+
+
+def test_undersized_allocation_rejected(st):
+    # a raw hipMalloc of 4096 bytes claimed to hold 3*200 doubles
+    import torch  # noqa: F401  (initialises HIP)
+    hip = ctypes.CDLL("libamdhip64.so")
+    ptr = VP()
+    assert hip.hipMalloc(ctypes.byref(ptr), ctypes.c_size_t(4096)) == 0
+    try:
+        lib = st.load()
+        rc = lib.steps_forces(ptr, None, None, 200, None)
+        assert rc == st.STEPS_E_INVAL
+        assert "pos needs" in _msg(lib), _msg(lib)
+    finally:
+        hip.hipFree(ptr)
+
+
+def test_aliasing_rejected_and_nothing_written(st):
+    ps = synth.config(1, n=300)
+    p, m, h = dev(ps.pos), dev(ps.mass), dev(ps.soft)
+    lib = st.load()
+    rc = lib.steps_forces(_p(p), _p(m), _p(h), 300, _p(p))
+    assert rc == st.STEPS_E_INVAL and "overlap" in _msg(lib)
+    assert np.array_equal(host(p), ps.pos)
+
+
+def test_nonfinite_with_flag(st):
+    import torch
+    ps = synth.config(1, n=300)
+    pos = ps.pos.copy()
+    pos[1, 17] = math.nan
+    ctx = st.Context(0, flags=st.STEPS_CHECK_FINITE)
+    acc = torch.full((3, 300), 5.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(st.StepsError) as ei:
+        st.steps_forces(dev(pos), dev(ps.mass), dev(ps.soft), acc=acc, ctx=ctx)
+    assert ei.value.code == st.STEPS_E_NONFINITE
+    assert np.all(host(acc) == 5.0)
+    ctx.close()
+
+
+def test_step_bad_cosmology_writes_nothing(st):
+    ps = synth.config(1, n=256)
+    p, v, m, h = dev(ps.pos), dev(ps.vel), dev(ps.mass), dev(ps.soft)
+    acc = st.steps_forces(p, m, h)
+    before = host(acc)
+    for bad in (dict(H0=-70.0), dict(G=-1.0)):
+        kw = dict(H0=70.0, omega_m=0.3, omega_l=0.7)
+        kw.update(bad)
+        with pytest.raises(st.StepsError) as ei:
+            st.steps_step(p, v, m, h, acc, 0.02, 0.001, st.Cosmology(**kw))
+        assert ei.value.code == st.STEPS_E_INVAL
+    with pytest.raises(st.StepsError):
+        st.steps_step(p, v, m, h, acc, 0.02, -0.05, st.Cosmology())  # a+da<0
+    with pytest.raises(st.StepsError):
+        st.steps_step(p, v, m, h, acc, float("nan"), 0.01, st.Cosmology())
+    assert np.array_equal(host(p), ps.pos)
+    assert np.array_equal(host(v), ps.vel)
+    assert np.array_equal(host(acc), before)
+
+
+def test_step_overlapping_state_rejected(st):
+    ps = synth.config(1, n=128)
+    p, m, h = dev(ps.pos), dev(ps.mass), dev(ps.soft)
+    acc = st.steps_forces(p, m, h)
+    with pytest.raises(st.StepsError) as ei:
+        st.steps_step(p, p, m, h, acc, 0.02, 0.001, st.Cosmology())
+    assert ei.value.code == st.STEPS_E_INVAL
+    assert np.array_equal(host(p), ps.pos)
+
+
+def test_bad_tile_rejected(st):
+    ctx = st.Context(0)
+    for args in ((3, 128, 1, 0), (4, 64, 1, 0), (4, 128, 0, 0), (4, 128, 1, 5)):
+        with pytest.raises(st.StepsError):
+            ctx.set_tile(*args)
+    ctx.set_precision("mixed")
+    with pytest.raises(st.StepsError):
+        ctx.set_tile(4, 128, 1, 1)   # FP64-only variant
+    ctx.close()
+
+
+def test_profile_timing_counts_launches(st):
+    ps = synth.config(1, n=1024)
+    ctx = st.Context(0, flags=st.STEPS_PROFILE)
+    p, m, h = dev(ps.pos), dev(ps.mass), dev(ps.soft)
+    for _ in range(3):
+        st.steps_forces(p, m, h, ctx=ctx)
+    ms, cnt = ctx.force_timing(reset=True)
+    assert cnt == 3 and ms > 0
+    assert ctx.force_timing() == (0.0, 0)
+    ctx.close()

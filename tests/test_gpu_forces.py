@@ -1,0 +1,183 @@
+"""GPU parity of the force kernels (C ABI) against the FP64 oracle.
+
+FP64 bar: per-particle relative force error <= 1e-12.  Mixed bar: median
+relative error <= 1e-5 (the max is printed)."""
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import clustered, dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def st():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1811_05903_amd as m
+    m.load()
+    return m
+
+
+def _report(name, err):
+    print("%s: n=%d median %.3e max %.3e" % (name, err.size, np.median(err),
+                                            err.max()), flush=True)
+
+
+def _gpu_forces(st, pos, mass, soft, ctx=None):
+    return host(st.steps_forces(dev(pos), dev(mass), dev(soft), ctx=ctx))
+
+
+@pytest.mark.parametrize("n", [2, 3, 17, 255, 256, 257, 1000, 5001])
+def test_fp64_small_sets(st, n):
+    ps = synth.config(1, n=n)
+    ref = oracle.forces(ps.pos, ps.mass, ps.soft)
+    got = _gpu_forces(st, ps.pos, ps.mass, ps.soft)
+    err = rel_err(got, ref)
+    _report("fp64 n=%d" % n, err)
+    assert err.max() <= FP64_TOL
+
+
+def test_n_zero_and_one(st):
+    import torch
+    e = torch.empty((3, 0), dtype=torch.float64, device="cuda")
+    st.steps_forces(e, torch.empty(0, dtype=torch.float64, device="cuda"),
+                    torch.empty(0, dtype=torch.float64, device="cuda"), acc=e)
+    acc = torch.full((3, 1), 7.0, dtype=torch.float64, device="cuda")
+    st.steps_forces(dev(np.ones((3, 1))), dev(np.ones(1)), dev(np.ones(1)), acc=acc)
+    assert np.all(host(acc) == 0.0)
+
+
+@pytest.mark.parametrize("zero_soft", [0.0, 0.3])
+def test_fp64_softened_and_coincident(st, zero_soft):
+    pos, mass, soft = clustered(3000, 17, zero_soft)
+    ref = oracle.forces(pos, mass, soft)
+    got = _gpu_forces(st, pos, mass, soft)
+    err = rel_err(got, ref)
+    _report("fp64 clustered zero_soft=%g" % zero_soft, err)
+    assert np.all(np.isfinite(got))
+    assert err.max() <= FP64_TOL
+
+
+def _variants(st):
+    out = []
+    for prec in ("fp64", "mixed", "kahan"):
+        ctx = st.Context(0, precision=prec)
+        for r, tj, var in {(1, 128, 0), (2, 128, 0), (4, 128, 0), (4, 256, 0),
+                           (8, 128, 0), (1, 128, 1), (2, 128, 1), (4, 128, 1),
+                           (4, 256, 1), (8, 128, 1), (2, 256, 0),
+                           (8, 256, 0)}:
+            for js in (1, 3, 7):
+                try:
+                    ctx.set_tile(r, tj, js, var)
+                except st.StepsError:
+                    continue
+                out.append((prec, r, tj, var, js))
+        ctx.close()
+    return out
+
+
+def test_every_launch_shape(st):
+    # ragged n (not a multiple of any tile or block), several j-splits
+    pos, mass, soft = clustered(1537, 23, 0.1)
+    ref = oracle.forces(pos, mass, soft)
+    shapes = _variants(st)
+    assert len(shapes) >= 3 * 14
+    ctxs = {p: st.Context(0, precision=p) for p in ("fp64", "mixed", "kahan")}
+    for prec, r, tj, var, js in shapes:
+        ctx = ctxs[prec]
+        ctx.set_tile(r, tj, js, var)
+        got = _gpu_forces(st, pos, mass, soft, ctx=ctx)
+        err = rel_err(got, ref)
+        tag = "%s r=%d tj=%d var=%d js=%d" % (prec, r, tj, var, js)
+        if prec == "fp64":
+            assert err.max() <= FP64_TOL, (tag, err.max())
+        else:
+            assert np.median(err) <= 1e-5, (tag, np.median(err))
+            assert err.max() <= 1e-3, (tag, err.max())
+    for c in ctxs.values():
+        c.close()
+
+
+def test_determinism_bitwise(st):
+    ps = synth.config(1, n=4096)
+    for prec in ("fp64", "mixed", "kahan"):
+        ctx = st.Context(0, precision=prec)
+        a = _gpu_forces(st, ps.pos, ps.mass, ps.soft, ctx)
+        b = _gpu_forces(st, ps.pos, ps.mass, ps.soft, ctx)
+        assert np.array_equal(a, b), prec
+        ctx.close()
+
+
+def test_default_context_c_entry_point(st):
+    # steps_forces (no ctx) through the raw C symbol on the null stream
+    import torch
+    ps = synth.config(1, n=700)
+    p, m, h = dev(ps.pos), dev(ps.mass), dev(ps.soft)
+    acc = torch.zeros((3, 700), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    rc = st.load().steps_forces(ctypes.c_void_p(p.data_ptr()),
+                                ctypes.c_void_p(m.data_ptr()),
+                                ctypes.c_void_p(h.data_ptr()), 700,
+                                ctypes.c_void_p(acc.data_ptr()))
+    assert rc == 0
+    torch.cuda.synchronize()
+    err = rel_err(host(acc), oracle.forces(ps.pos, ps.mass, ps.soft))
+    assert err.max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("prec", ["mixed", "kahan"])
+def test_mixed_config1(st, prec):
+    ps = synth.config(1, n=4096)
+    ref = oracle.forces(ps.pos, ps.mass, ps.soft)
+    ctx = st.Context(0, precision=prec)
+    got = _gpu_forces(st, ps.pos, ps.mass, ps.soft, ctx)
+    ctx.close()
+    err = rel_err(got, ref)
+    _report("%s config1" % prec, err)
+    assert np.median(err) <= 1e-5
+
+
+def test_full_size_config2_sampled(st):
+    # N = 2^18 in the default launch shape; oracle on 256 sampled particles
+    ps = synth.config(2)
+    got = _gpu_forces(st, ps.pos, ps.mass, ps.soft)
+    idx = np.random.default_rng(2).choice(ps.n, 256, replace=False)
+    ref = oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx)
+    err = rel_err(got[:, idx], ref)
+    _report("fp64 config2 sampled", err)
+    assert err.max() <= FP64_TOL
+
+
+def test_full_size_config3_sampled_all_modes(st):
+    # N = 2^21, default launch shapes; oracle on 64 sampled particles
+    ps = synth.config(3)
+    idx = np.random.default_rng(3).choice(ps.n, 64, replace=False)
+    ref = oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx)
+    p, m, h = dev(ps.pos), dev(ps.mass), dev(ps.soft)
+    for prec in ("fp64", "mixed", "kahan"):
+        ctx = st.Context(0, precision=prec)
+        got = host(st.steps_forces(p, m, h, ctx=ctx))[:, idx]
+        ctx.close()
+        err = rel_err(got, ref)
+        _report("%s config3 sampled" % prec, err)
+        if prec == "fp64":
+            assert err.max() <= FP64_TOL
+        else:
+            assert np.median(err) <= 1e-5
+
+
+def test_potential_parity(st):
+    pos, mass, soft = clustered(2000, 31, 0.2)
+    ref = oracle.potential(pos, mass, soft)
+    got = host(st.steps_potential(dev(pos), dev(mass), dev(soft)))
+    err = np.abs(got - ref) / np.abs(ref)
+    _report("potential", err)
+    assert err.max() <= FP64_TOL

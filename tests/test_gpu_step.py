@@ -1,0 +1,129 @@
+"""GPU parity of the KDK step (C ABI steps_step) against the oracle, and the
+integrator's closed-form pins run through the GPU path."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def st():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1811_05903_amd as m
+    m.load()
+    return m
+
+
+def _cos(ps):
+    c = ps.cosmo
+    return (oracle.Cosmology(c.H0, c.omega_m, c.omega_l, c.omega_r),
+            None)
+
+
+def _pair(st, c, newtonian=False, G=None):
+    o = oracle.Cosmology(c.H0, c.omega_m, c.omega_l, c.omega_r,
+                         G=G, newtonian_test=newtonian)
+    g = st.Cosmology(c.H0, c.omega_m, c.omega_l, c.omega_r,
+                     G=G or 0.0, newtonian_test=newtonian)
+    return o, g
+
+
+@pytest.mark.parametrize("n,steps", [(1024, 100), (4096, 10)])
+def test_config1_trajectory_parity(st, n, steps):
+    ps = synth.config(1, n=n)
+    grid = ps.a_grid()[: steps + 1]
+    oc, gc = _pair(st, ps.cosmo)
+    p_or, v_or, S_or = oracle.run(ps.pos, ps.vel, ps.mass, ps.soft, grid, oc)
+    p, v = dev(ps.pos), dev(ps.vel)
+    acc = st.run(p, v, dev(ps.mass), dev(ps.soft), grid, gc)
+    p, v, acc = host(p), host(v), host(acc)
+    dx = np.linalg.norm(p - p_or, axis=0) / ps.soft
+    dv = np.linalg.norm(v - v_or, axis=0) / np.linalg.norm(v_or, axis=0).max()
+    dS = np.linalg.norm(acc - S_or, axis=0) / np.linalg.norm(S_or, axis=0)
+    print("config1 n=%d steps=%d: |dx|/h max %.2e, |dv|/max|v| %.2e, "
+          "dS/S median %.2e max %.2e" % (n, steps, dx.max(), dv.max(),
+                                         np.median(dS), dS.max()), flush=True)
+    assert dx.max() < 1e-9
+    assert dv.max() < 1e-9
+    assert np.median(dS) < 1e-10
+
+
+def test_eds_lone_particle_closed_form_gpu(st):
+    c = synth.Cosmo(H0=70.0, omega_m=1.0, omega_l=0.0)
+    _, gc = _pair(st, c)
+    x1 = np.array([[3.0], [-1.0], [2.0]])
+    a1, a2, ns = 0.02, 0.2, 400
+    grid = a1 * (a2 / a1) ** (np.arange(ns + 1) / ns)
+    p, v = dev(x1), dev(np.zeros((3, 1)))
+    st.run(p, v, dev(np.ones(1)), dev(np.zeros(1)), grid, gc)
+    exact = x1[:, 0] * (2.0 / 3.0 * math.sqrt(a2 / a1) + 1.0 / 3.0 * (a1 / a2))
+    err = np.linalg.norm(host(p)[:, 0] - exact) / np.linalg.norm(exact)
+    assert err < 5e-5
+
+
+def _kepler(ecc):
+    m1, m2 = 0.75, 0.25
+    rp = 1.0 - ecc
+    vp = math.sqrt((1.0 + ecc) / rp)
+    rel_x, rel_v = np.array([rp, 0, 0]), np.array([0, vp, 0])
+    pos = np.stack([-m2 * rel_x, m1 * rel_x], axis=1)
+    vel = np.stack([-m2 * rel_v, m1 * rel_v], axis=1)
+    return pos, vel, np.array([m1, m2]), np.zeros(2)
+
+
+def test_newtonian_kepler_parity_and_reversibility(st):
+    pos, vel, mass, soft = _kepler(0.5)
+    c = synth.Cosmo()
+    oc, gc = _pair(st, c, newtonian=True, G=1.0)
+    grid = np.linspace(0.0, 2 * math.pi, 801)
+    p_or, v_or, _ = oracle.run(pos, vel, mass, soft, grid, oc)
+    p, v = dev(pos), dev(vel)
+    m, h = dev(mass), dev(soft)
+    acc = st.run(p, v, m, h, grid, gc)
+    np.testing.assert_allclose(host(p), p_or, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(host(v), v_or, rtol=0, atol=1e-11)
+    # back again with negative steps
+    for k in range(800, 0, -1):
+        st.steps_step(p, v, m, h, acc, grid[k], grid[k - 1] - grid[k], gc)
+    np.testing.assert_allclose(host(p), pos, atol=1e-11)
+    np.testing.assert_allclose(host(v), vel, atol=1e-11)
+
+
+def test_comoving_reversibility(st):
+    ps = synth.config(1, n=512)
+    _, gc = _pair(st, ps.cosmo)
+    p, v = dev(ps.pos), dev(ps.vel + 1e-3)
+    v0 = host(v)
+    m, h = dev(ps.mass), dev(ps.soft)
+    grid = ps.a_grid()[:21]
+    acc = st.run(p, v, m, h, grid, gc)
+    vmax = np.abs(host(v)).max()      # velocities reached at the far end
+    for k in range(20, 0, -1):
+        st.steps_step(p, v, m, h, acc, grid[k], grid[k - 1] - grid[k], gc)
+    scale = np.abs(ps.pos).max()
+    assert np.abs(host(p) - ps.pos).max() < 1e-12 * scale
+    assert np.abs(host(v) - v0).max() < 1e-10 * vmax
+
+
+@pytest.mark.parametrize("prec", ["mixed", "kahan"])
+def test_mixed_step_close_to_fp64(st, prec):
+    ps = synth.config(1, n=2048)
+    _, gc = _pair(st, ps.cosmo)
+    grid = ps.a_grid()[:11]
+    res = {}
+    for mode in ("fp64", prec):
+        ctx = st.Context(0, precision=mode)
+        p, v = dev(ps.pos), dev(ps.vel)
+        st.run(p, v, dev(ps.mass), dev(ps.soft), grid, gc, ctx=ctx)
+        res[mode] = host(p)
+        ctx.close()
+    dx = np.linalg.norm(res[prec] - res["fp64"], axis=0) / ps.soft
+    print("%s vs fp64 after 10 steps: |dx|/h max %.2e" % (prec, dx.max()))
+    assert dx.max() < 1e-4
