@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-modes", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="finish with one device copy of MIB MiB (a kernel of "
+                         "known traffic, to scale HBM byte counters)")
     return ap.parse_args()
 
 
@@ -118,6 +121,7 @@ def main():
         % (args.steps, ms_step, value, kern_ms, force_cnt))
     assert bool(torch.isfinite(pos).all()) and bool(torch.isfinite(acc).all())
 
+    traffic = profiled_traffic(args.precision, tile, args.workload)
     out = {
         "metric": "pair interactions/s (ordered pairs, whole KDK step)",
         "value": value,
@@ -139,7 +143,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None,
+                     "traffic": traffic,
                      "kernel": "k_force_%s" % ("f64" if args.precision == "fp64" else "mixed"),
                      "kernel_ms": kern_ms,
                      "flop_per_pair": FLOP_PER_PAIR},
@@ -149,10 +153,11 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         rng = np.random.default_rng(12345)
-        probe = rng.choice(n, 64, replace=False)
+        oracle.forces(ps.pos, ps.mass, ps.soft, idx=rng.choice(n, 16, replace=False))
+        probe = rng.choice(n, 512, replace=False)
         t = time.perf_counter()
         oracle.forces(ps.pos, ps.mass, ps.soft, idx=probe)
-        rate = 64 * n / (time.perf_counter() - t)
+        rate = 512 * n / (time.perf_counter() - t)
         m = int(min(n, max(64, rate * args.cpu_seconds / n)))
         idx = np.sort(rng.choice(n, m, replace=False))
         log("cpu baseline: oracle on %d sampled rows (%d threads)" % (m, oracle.num_threads()))
@@ -177,7 +182,38 @@ def main():
             big_rows = (bidx, oracle.forces(big.pos, big.mass, big.soft, idx=bidx))
         out["modes_n2e21"] = mode_table(st, big, big_rows, dev)
     ctx.close()
+    if args.copy_calibration:
+        nb = args.copy_calibration << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d MiB read + %d MiB written" % (
+            args.copy_calibration, args.copy_calibration))
     print(json.dumps(out), flush=True)
+
+
+def profiled_traffic(precision, tile, workload):
+    """HBM bytes per force launch from the committed rocprofv3 summary of
+    this kernel and launch shape, or None if there is none or the kernel
+    source has changed since it was taken."""
+    import hashlib
+    cls = "f64" if precision == "fp64" else "mixed"
+    tag = "e2" if tile["variant"] == 0 else "e1"
+    path = os.path.join(ROOT, "profiles", "k_force_%s_r%d_tj%d_%s_workload%d.md"
+                        % (cls, tile["r"], tile["tj"], tag, workload))
+    if not os.path.exists(path):
+        return None
+    src = os.path.join(ROOT, "paper_1811_05903_amd", "csrc", "steps_kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    traffic, ok = None, False
+    for line in open(path):
+        if line.startswith("traffic_bytes_per_launch:"):
+            traffic = float(line.split(":", 1)[1])
+        if line.startswith("source_sha256:"):
+            ok = line.split(":", 1)[1].split()[0] == digest
+    return traffic if ok else None
 
 
 def mode_table(st, ps, rows, dev):
