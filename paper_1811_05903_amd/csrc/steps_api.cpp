@@ -26,6 +26,8 @@
 namespace {
 
 constexpr int64_t kMaxN = int64_t(1) << 30;
+// below this size the spatial sort costs more than the culling saves
+constexpr int64_t kSortMinN = 32768;
 
 thread_local std::string t_err;
 
@@ -72,6 +74,7 @@ struct steps_ctx {
   steps_tile tile = {0, 0, 0, 0};
   Buffer part;     // j-split partial sums
   Buffer shadow;   // FP32 shadow of the inputs
+  Buffer arena;    // spatial-sort scratch (keys, permutation, sorted copy)
   int *flag = nullptr;  // device int for the finite check
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
   std::vector<hipEvent_t> prof_pool;
@@ -169,25 +172,33 @@ int variant_tj(int cls, int r) {
   return 0;
 }
 
-// Launch shape: a forced tile, else the heuristic.  i-blocks of 256*r
-// particles; r is lowered for small n so that there are at least 256
-// i-blocks where possible; the j range is then split so that the grid holds
-// about 2048 workgroups (8 per CU), keeping every split at least two tiles.
+// Launch shape: a forced tile, else the heuristic, tuned on MI355X at
+// N = 2^18 and 2^21: FP64 r = 4, mixed r = 2 (fewer registers, more waves
+// to pair up FP32 issue); r is lowered for small n so that there are at
+// least 256 i-blocks where possible; the j range is then split so that the
+// grid holds about 8192 (FP64) or 16384 (mixed) workgroups, keeping every
+// split at least two tiles.  Culled (sorted) variants from kSortMinN up; in
+// FP64 the r^-3 correction stops at first order there (variant 3).
 steps_tile choose_tile(const steps_ctx *c, int64_t n) {
   const int cls = prec_class(c->precision);
   steps_tile t;
   if (c->tile_forced) {
     t = c->tile;
   } else {
-    int r = cls == steps::kClassF64 ? 4 : 8;
+    const bool f64 = cls == steps::kClassF64;
+    int r = f64 ? 4 : 2;
     while (r > 1 && (n + 256LL * r - 1) / (256LL * r) < 256) r /= 2;
     t.r = r;
     t.tj = variant_tj(cls, r);
     const int64_t nb = std::max<int64_t>(1, (n + 256LL * r - 1) / (256LL * r));
-    int64_t js = (2048 + nb - 1) / nb;
+    const int64_t target = f64 ? 8192 : 16384;
+    int64_t js = (target + nb - 1) / nb;
     js = std::min<int64_t>(js, std::max<int64_t>(1, n / (2LL * t.tj)));
-    t.jsplit = (int)std::max<int64_t>(1, std::min<int64_t>(js, 1024));
+    t.jsplit = (int)std::max<int64_t>(1, std::min<int64_t>(js, 64));
     t.variant = 0;
+    if (n >= kSortMinN) {
+      t.variant = steps::kVarCull | (f64 ? steps::kVarNoE2 : 0);
+    }
   }
   return t;
 }
@@ -225,18 +236,30 @@ int prof_end(steps_ctx *c, hipEvent_t *ev) {
   return STEPS_OK;
 }
 
+// Sub-allocation of one scratch buffer.
+struct Carve {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    const size_t at = off;
+    off += (bytes + 255) & ~size_t(255);
+    return at;
+  }
+};
+
 // Enqueue acc <- S(pos) in the context's precision.  Arguments validated.
 int run_forces(steps_ctx *c, const double *pos, const double *mass,
                const double *soft, int n, double *acc) {
   if (n == 0) return STEPS_OK;
   const int cls = prec_class(c->precision);
   const steps_tile t = choose_tile(c, n);
-  const steps::ForceVariant *v = steps::find_force_variant(cls, t.r, t.tj, t.variant);
+  const steps::ForceVariant *v =
+      steps::find_force_variant(cls, t.r, t.tj, t.variant);
   if (!v) {
     return fail(STEPS_E_INVAL,
                 "no compiled force kernel with r=%d tj=%d variant=%d", t.r,
                 t.tj, t.variant);
   }
+  const bool cull = (t.variant & steps::kVarCull) != 0;
   int chunk = 0, js = 1;
   split_j(n, t.tj, std::max(1, t.jsplit), &chunk, &js);
   steps::ForceLaunch L;
@@ -246,14 +269,70 @@ int run_forces(steps_ctx *c, const double *pos, const double *mass,
   L.out = acc;
   L.kahan = c->precision == STEPS_MIXED_KAHAN;
   int rc;
-  if (js > 1) {
+  hipError_t e;
+  if (js > 1 || cull) {
     rc = ensure(c, c->part, (size_t)js * 3 * (size_t)n * sizeof(double),
                 "partial-sum");
     if (rc) return rc;
     L.out = (double *)c->part.p;
   }
-  hipError_t e;
-  if (cls == steps::kClassMixed) {
+  const int *perm = nullptr;
+  if (cull) {
+    // Morton order: bbox -> keys -> stable sort -> sorted copy -> tile boxes
+    size_t cub_bytes = 0;
+    e = steps::sort_pairs(nullptr, &cub_bytes, nullptr, nullptr, nullptr,
+                          nullptr, n, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "radix sort size query");
+    const int ntiles = (n + t.tj - 1) / t.tj;
+    Carve cv;
+    const size_t o_box = cv.take(6 * sizeof(double));
+    const size_t o_bpart = cv.take((size_t)steps::bbox_blocks(n) * 6 * sizeof(double));
+    const size_t o_k0 = cv.take((size_t)n * 8), o_k1 = cv.take((size_t)n * 8);
+    const size_t o_v0 = cv.take((size_t)n * 4), o_v1 = cv.take((size_t)n * 4);
+    const size_t o_cub = cv.take(cub_bytes);
+    const size_t o_info = cv.take((size_t)ntiles * 8 * sizeof(double));
+    const size_t o_soa = cv.take(cls == steps::kClassF64
+                                     ? 5 * (size_t)n * sizeof(double)
+                                     : 5 * (size_t)n * sizeof(float));
+    if ((rc = ensure(c, c->arena, cv.off, "sort"))) return rc;
+    char *base = (char *)c->arena.p;
+    double *box = (double *)(base + o_box);
+    auto *k0 = (unsigned long long *)(base + o_k0);
+    auto *k1 = (unsigned long long *)(base + o_k1);
+    int *v0 = (int *)(base + o_v0), *v1 = (int *)(base + o_v1);
+    double *info = (double *)(base + o_info);
+    if ((e = steps::launch_bbox(pos, n, (double *)(base + o_bpart), box,
+                                c->stream)) != hipSuccess ||
+        (e = steps::launch_morton(pos, n, box, k0, v0, c->stream)) !=
+            hipSuccess) {
+      return hip_fail(e, "sort-key kernel launch");
+    }
+    e = steps::sort_pairs(base + o_cub, &cub_bytes, k0, k1, v0, v1, n,
+                          c->stream);
+    if (e != hipSuccess) return hip_fail(e, "radix sort");
+    perm = v1;
+    if (cls == steps::kClassF64) {
+      double *sorted = (double *)(base + o_soa);
+      e = steps::launch_gather(pos, mass, soft, perm, n, sorted, nullptr,
+                               c->stream);
+      if (e == hipSuccess) {
+        e = steps::launch_tile_info_f64(sorted, n, t.tj, info, c->stream);
+      }
+      L.pos = sorted;
+      L.mass = sorted + 3 * (size_t)n;
+      L.soft = sorted + 4 * (size_t)n;
+    } else {
+      float *shadow = (float *)(base + o_soa);
+      e = steps::launch_gather(pos, mass, soft, perm, n, nullptr, shadow,
+                               c->stream);
+      if (e == hipSuccess) {
+        e = steps::launch_tile_info_f32(shadow, n, t.tj, info, c->stream);
+      }
+      L.shadow = shadow;
+    }
+    if (e != hipSuccess) return hip_fail(e, "gather kernel launch");
+    L.tinfo = info;
+  } else if (cls == steps::kClassMixed) {
     rc = ensure(c, c->shadow, 5 * (size_t)n * sizeof(float), "FP32 shadow");
     if (rc) return rc;
     e = steps::launch_shadow(pos, mass, soft, n, (float *)c->shadow.p,
@@ -270,7 +349,10 @@ int run_forces(steps_ctx *c, const double *pos, const double *mass,
   e = v->launch(L, c->stream);
   if (e != hipSuccess) return hip_fail(e, "force kernel launch");
   if ((rc = prof_end(c, ev))) return rc;
-  if (js > 1) {
+  if (cull) {
+    e = steps::launch_reduce_scatter(L.out, js, n, perm, acc, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
+  } else if (js > 1) {
     e = steps::launch_reduce_partials(L.out, js, n, acc, c->stream);
     if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
   }
@@ -417,6 +499,7 @@ int steps_ctx_destroy(steps_ctx *c) {
   for (auto ev : c->prof_pool) (void)hipEventDestroy(ev);
   if (c->part.p) (void)hipFree(c->part.p);
   if (c->shadow.p) (void)hipFree(c->shadow.p);
+  if (c->arena.p) (void)hipFree(c->arena.p);
   if (c->flag) (void)hipFree(c->flag);
   delete c;
   return rc;

@@ -1,0 +1,477 @@
+// gfx950 pair-sum kernels of libsteps: the all-pairs spline-softened sum of
+// StePS (Racz et al. 2018, Sec. 2.2 Eqs. 3, 4 and 8),
+//   S_i = sum_{j != i} m_j F(r_ij, h_i + h_j) (x_j - x_i) / r_ij.
+//
+// Layout common to every variant:
+//   * a workgroup is 256 lanes = 4 wave64.  Wave w of block b owns the
+//     64*R consecutive particles starting at b*256*R + w*64*R; lane l holds
+//     i = start + 64*r + l for r < R in registers (coalesced loads/stores);
+//   * grid.y splits the j range into jsplit chunks (multiples of TJ); each
+//     chunk streams through LDS in tiles of TJ particles, staged with
+//     coalesced SoA reads and read back by every lane as broadcasts;
+//   * a lane sums a tile's terms into a per-tile partial and adds it to its
+//     running total after the tile (blocked summation: rounding grows with
+//     TJ + N/TJ rather than N; in FP64 the running total is also
+//     compensated); no atomics, so a launch shape gives a
+//     bitwise-reproducible result.
+//
+// The softened branch of Eq. 4 applies only to pairs closer than
+// h_i + h_j.  Two ways to handle it:
+//   * CULL = false: every pair is tested (h add, h^2, compare) and a wave
+//     takes the softened branch only when one of its lanes needs it;
+//   * CULL = true: particles arrive sorted along a space-filling curve, the
+//     host has computed each j-tile's bounding box and largest softening,
+//     and each wave computes the same for its own i.  When the boxes are
+//     farther apart than the two largest softenings combined, no pair of the
+//     (wave, tile) block can be softened or coincident, and the wave runs a
+//     loop with the Newtonian weight only -- no per-pair test at all.
+//     Otherwise it runs the tested loop.
+
+#include "steps_internal.h"
+
+namespace steps {
+namespace {
+
+// ---------------------------------------------------------------------------
+// FP64 pair weight, Newtonian branch (r >= h): w = m r^-3.  v_rsq_f64 gives
+// y ~ r^-1 to about 2^-24 (measured on gfx950); with e = 1 - r2 y^2,
+//   r^-3 = y^3 (1 - e)^(-3/2) = y^3 (1 + 3/2 e + 15/8 e^2 + O(e^3)).
+// E2 = true keeps the e^2 term (residual below 2^-68).  E2 = false stops at
+// the linear term: the residual 15/8 e^2 is at most ~2e-14 relative per
+// pair and about 1e-15 on average, and the weight costs one accumulate-form
+// FMA with a literal instead of a two-constant polynomial.
+// ---------------------------------------------------------------------------
+template <bool E2>
+__device__ __forceinline__ double newton_w64(double r2, double m) {
+  double y = __builtin_amdgcn_rsq(r2);
+  double y2 = y * y;
+  double e = fma(-r2, y2, 1.0);
+  double t = (m * y) * y2;
+  if (E2) return t * fma(e, fma(e, 1.875, 1.5), 1.0);
+  return fma(t * e, 1.5, t);
+}
+
+// Softened branch of Eq. 4 divided by r, with u = r/h (h = h_i + h_j):
+//   u < 1/2      : (1/h^3) (32/3 - 38.4 u^2 + 32 u^3)
+//   1/2 <= u < 1 : (1/h^3) (64/3 - 48 u + 38.4 u^2 - 32/3 u^3) - 1/(15 r^3)
+// Zero separation contributes nothing (the j != i exclusion of Eq. 8).
+// Only reached when r2 <= h^2, so h > 0 whenever r2 > 0.
+__device__ __noinline__ double soft_w64(double r2, double h, double m) {
+  if (r2 == 0.0) return 0.0;
+  double y = __builtin_amdgcn_rsq(r2);
+  double e = fma(-r2, y * y, 1.0);
+  // r^-1 = y (1 - e)^(-1/2) = y (1 + e/2 + 3/8 e^2 + ...)
+  double rinv = y * fma(e, fma(e, 0.375, 0.5), 1.0);
+  double r = r2 * rinv;
+  double hinv = 1.0 / h;
+  double u = r * hinv;
+  double hinv3 = hinv * hinv * hinv;
+  if (u < 0.5) {
+    return m * hinv3 * fma(u * u, fma(32.0, u, -38.4), 32.0 / 3.0);
+  }
+  double p = fma(u, fma(u, fma(u, -32.0 / 3.0, 38.4), -48.0), 64.0 / 3.0);
+  return m * fma(hinv3, p, -(rinv * rinv * rinv) * (1.0 / 15.0));
+}
+
+__device__ __noinline__ float soft_w32(float r2, float h, float m) {
+  if (r2 == 0.0f) return 0.0f;
+  float rinv = __builtin_amdgcn_rsqf(r2);
+  float r = r2 * rinv;
+  float hinv = 1.0f / h;
+  float u = r * hinv;
+  float hinv3 = hinv * hinv * hinv;
+  if (u < 0.5f) {
+    return m * hinv3 * fmaf(u * u, fmaf(32.0f, u, -38.4f), 32.0f / 3.0f);
+  }
+  float p = fmaf(u, fmaf(u, fmaf(u, -32.0f / 3.0f, 38.4f), -48.0f), 64.0f / 3.0f);
+  return m * fmaf(hinv3, p, -(rinv * rinv * rinv) * (1.0f / 15.0f));
+}
+
+// s + c += x with the rounding error of the addition kept in c (Knuth's
+// TwoSum, branch-free).  Used to add each tile's partial into the running
+// total: in spatial order the running sum can pass through values far
+// larger than the final one (the pull of one side of a particle arrives
+// before the other side's), and plain addition would lose ~1e-12 of it.
+__device__ __forceinline__ void two_sum_add(double &s, double &c, double x) {
+  const double t = s + x;
+  const double bp = t - s;
+  c += (s - (t - bp)) + (x - bp);
+  s = t;
+}
+
+// ---------------------------------------------------------------------------
+// wave-level helpers for the culling test
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+// a value equal on every lane, moved to scalar registers
+__device__ __forceinline__ double uniform(double v) {
+  unsigned long long b = __double_as_longlong(v);
+  unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+  unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+
+// Wave box: (xlo, ylo, zlo, xhi, yhi, zhi, hmax) over the wave's valid i.
+template <int R, typename T>
+__device__ __forceinline__ void wave_box(const T *xi, const T *yi, const T *zi,
+                                         const T *hi, const bool *valid,
+                                         double wb[7]) {
+  double lo[3] = {INFINITY, INFINITY, INFINITY};
+  double up[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double hm = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (valid[r]) {
+      lo[0] = fmin(lo[0], (double)xi[r]); up[0] = fmax(up[0], (double)xi[r]);
+      lo[1] = fmin(lo[1], (double)yi[r]); up[1] = fmax(up[1], (double)yi[r]);
+      lo[2] = fmin(lo[2], (double)zi[r]); up[2] = fmax(up[2], (double)zi[r]);
+      hm = fmax(hm, (double)hi[r]);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    wb[d] = uniform(wave_min(lo[d]));
+    wb[3 + d] = uniform(wave_max(up[d]));
+  }
+  wb[6] = uniform(wave_max(hm));
+}
+
+// True when no pair between the wave box and the tile box
+// (tile info: xlo, ylo, zlo, xhi, yhi, zhi, hmax) can be closer than the
+// largest combined softening, nor coincide.
+__device__ __forceinline__ bool tile_is_far(const double *__restrict__ ti,
+                                            const double wb[7]) {
+  const double gx = fmax(0.0, fmax(ti[0] - wb[3], wb[0] - ti[3]));
+  const double gy = fmax(0.0, fmax(ti[1] - wb[4], wb[1] - ti[4]));
+  const double gz = fmax(0.0, fmax(ti[2] - wb[5], wb[2] - ti[5]));
+  const double d2 = gx * gx + gy * gy + gz * gz;
+  const double hs = ti[6] + wb[6];
+  const bool far = d2 > fmax(hs * hs * (1.0 + 1e-6), 1e-30);
+  return __builtin_amdgcn_readfirstlane((int)far) != 0;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 kernel.  LDS tile: per j three double2 = (x, y), (z, m), (h, -).
+// ---------------------------------------------------------------------------
+template <int R, int TJ, bool E2, bool CULL>
+__global__ __launch_bounds__(kBlock) void k_force_f64(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ soft, int n, int jchunk,
+    const double *__restrict__ tinfo, double *__restrict__ out) {
+  __shared__ double2 tile[3 * TJ];
+  const int tid = threadIdx.x;
+  const int ibase = blockIdx.x * (kBlock * R) + (tid >> 6) * (64 * R) + (tid & 63);
+  const int jbeg = blockIdx.y * jchunk;
+  const int jend = min(n, jbeg + jchunk);
+  const double *X = pos, *Y = pos + n, *Z = pos + 2 * (size_t)n;
+
+  double xi[R], yi[R], zi[R], hi[R];
+  double ax[R], ay[R], az[R], cx[R], cy[R], cz[R];  // total + compensation
+  bool valid[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = ibase + 64 * r;
+    valid[r] = i < n;
+    xi[r] = valid[r] ? X[i] : 0.0;
+    yi[r] = valid[r] ? Y[i] : 0.0;
+    zi[r] = valid[r] ? Z[i] : 0.0;
+    hi[r] = valid[r] ? soft[i] : 0.0;
+    ax[r] = ay[r] = az[r] = cx[r] = cy[r] = cz[r] = 0.0;
+  }
+  double wb[7];
+  if (CULL) wave_box<R, double>(xi, yi, zi, hi, valid, wb);
+
+  for (int jt = jbeg; jt < jend; jt += TJ) {
+    __syncthreads();
+    for (int k = tid; k < TJ; k += kBlock) {
+      // entries past the end repeat the last particle with zero mass: they
+      // add nothing and never sit outside the tile's box
+      const int j = min(jt + k, jend - 1);
+      const double mj = (jt + k < jend) ? mass[j] : 0.0;
+      tile[3 * k] = double2{X[j], Y[j]};
+      tile[3 * k + 1] = double2{Z[j], mj};
+      tile[3 * k + 2] = double2{soft[j], 0.0};
+    }
+    __syncthreads();
+
+    bool far = false;
+    if (CULL) far = tile_is_far(tinfo + (size_t)(jt / TJ) * 8, wb);
+
+    double tx[R], ty[R], tz[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) tx[r] = ty[r] = tz[r] = 0.0;
+
+    if (far) {
+#pragma unroll 2
+      for (int k = 0; k < TJ; ++k) {
+        const double2 a = tile[3 * k], b = tile[3 * k + 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double dx = a.x - xi[r], dy = a.y - yi[r], dz = b.x - zi[r];
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          const double w = newton_w64<E2>(r2, b.y);
+          tx[r] = fma(w, dx, tx[r]);
+          ty[r] = fma(w, dy, ty[r]);
+          tz[r] = fma(w, dz, tz[r]);
+        }
+      }
+    } else {
+#pragma unroll 2
+      for (int k = 0; k < TJ; ++k) {
+        const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
+        const double xj = a.x, yj = a.y, zj = b.x, mj = b.y, hj = c.x;
+        double dx[R], dy[R], dz[R], r2[R], w[R];
+        bool sf[R];
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          dx[r] = xj - xi[r];
+          dy[r] = yj - yi[r];
+          dz[r] = zj - zi[r];
+          r2[r] = fma(dz[r], dz[r], fma(dy[r], dy[r], dx[r] * dx[r]));
+          const double h = hj + hi[r];
+          sf[r] = r2[r] <= h * h;  // softened, or zero separation
+          any |= sf[r];
+          w[r] = newton_w64<E2>(r2[r], mj);
+        }
+        if (any) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (sf[r]) w[r] = soft_w64(r2[r], hj + hi[r], mj);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          tx[r] = fma(w[r], dx[r], tx[r]);
+          ty[r] = fma(w[r], dy[r], ty[r]);
+          tz[r] = fma(w[r], dz[r], tz[r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      two_sum_add(ax[r], cx[r], tx[r]);
+      two_sum_add(ay[r], cy[r], ty[r]);
+      two_sum_add(az[r], cz[r], tz[r]);
+    }
+  }
+
+  double *o = out + (size_t)blockIdx.y * 3 * (size_t)n;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = ibase + 64 * r;
+    if (i < n) {
+      o[i] = ax[r] + cx[r];
+      o[(size_t)n + i] = ay[r] + cy[r];
+      o[2 * (size_t)n + i] = az[r] + cz[r];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: pair arithmetic in FP32 on an FP32 shadow [5][n]
+// (x, y, z, m, h); v_rsq_f32 (~2^-23) used as is.  Each tile's FP32 partial
+// is added into an FP64 accumulator, or into a Kahan-compensated FP32
+// (sum, compensation) pair.  The inner loops use only two-operand VGPR
+// forms of the FP32 ops, which gfx950 issues from two waves per cycle.
+// LDS tile: float4 (x, y, z, m) and float h.
+// ---------------------------------------------------------------------------
+template <int R, int TJ, bool KAHAN, bool CULL>
+__global__ __launch_bounds__(kBlock) void k_force_mixed(
+    const float *__restrict__ shadow, int n, int jchunk,
+    const double *__restrict__ tinfo, double *__restrict__ out) {
+  __shared__ float4 tpos[TJ];
+  __shared__ float tsoft[TJ];
+  const int tid = threadIdx.x;
+  const int ibase = blockIdx.x * (kBlock * R) + (tid >> 6) * (64 * R) + (tid & 63);
+  const int jbeg = blockIdx.y * jchunk;
+  const int jend = min(n, jbeg + jchunk);
+  const float *X = shadow, *Y = shadow + n, *Z = shadow + 2 * (size_t)n;
+  const float *M = shadow + 3 * (size_t)n, *H = shadow + 4 * (size_t)n;
+
+  float xi[R], yi[R], zi[R], hi[R];
+  bool valid[R];
+  double ax[R], ay[R], az[R];                      // FP64 accumulation
+  float sx[R], sy[R], sz[R], cx[R], cy[R], cz[R];  // Kahan accumulation
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = ibase + 64 * r;
+    valid[r] = i < n;
+    xi[r] = valid[r] ? X[i] : 0.0f;
+    yi[r] = valid[r] ? Y[i] : 0.0f;
+    zi[r] = valid[r] ? Z[i] : 0.0f;
+    hi[r] = valid[r] ? H[i] : 0.0f;
+    ax[r] = ay[r] = az[r] = 0.0;
+    sx[r] = sy[r] = sz[r] = cx[r] = cy[r] = cz[r] = 0.0f;
+  }
+  double wb[7];
+  if (CULL) wave_box<R, float>(xi, yi, zi, hi, valid, wb);
+
+  for (int jt = jbeg; jt < jend; jt += TJ) {
+    __syncthreads();
+    for (int k = tid; k < TJ; k += kBlock) {
+      const int j = min(jt + k, jend - 1);
+      const float mj = (jt + k < jend) ? M[j] : 0.0f;
+      tpos[k] = float4{X[j], Y[j], Z[j], mj};
+      tsoft[k] = H[j];
+    }
+    __syncthreads();
+
+    bool far = false;
+    if (CULL) far = tile_is_far(tinfo + (size_t)(jt / TJ) * 8, wb);
+
+    float tx[R], ty[R], tz[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) tx[r] = ty[r] = tz[r] = 0.0f;
+
+    if (far) {
+#pragma unroll 2
+      for (int k = 0; k < TJ; ++k) {
+        const float4 p = tpos[k];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const float dx = p.x - xi[r], dy = p.y - yi[r], dz = p.z - zi[r];
+          const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          const float y = __builtin_amdgcn_rsqf(r2);
+          const float w = (p.w * y) * (y * y);
+          tx[r] = fmaf(w, dx, tx[r]);
+          ty[r] = fmaf(w, dy, ty[r]);
+          tz[r] = fmaf(w, dz, tz[r]);
+        }
+      }
+    } else {
+#pragma unroll 2
+      for (int k = 0; k < TJ; ++k) {
+        const float4 p = tpos[k];
+        const float hj = tsoft[k];
+        float dx[R], dy[R], dz[R], r2[R], w[R];
+        bool sf[R];
+        bool any = false;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          dx[r] = p.x - xi[r];
+          dy[r] = p.y - yi[r];
+          dz[r] = p.z - zi[r];
+          r2[r] = fmaf(dz[r], dz[r], fmaf(dy[r], dy[r], dx[r] * dx[r]));
+          const float h = hj + hi[r];
+          sf[r] = r2[r] <= h * h;
+          any |= sf[r];
+          const float y = __builtin_amdgcn_rsqf(r2[r]);
+          w[r] = (p.w * y) * (y * y);
+        }
+        if (any) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (sf[r]) w[r] = soft_w32(r2[r], hj + hi[r], p.w);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          tx[r] = fmaf(w[r], dx[r], tx[r]);
+          ty[r] = fmaf(w[r], dy[r], ty[r]);
+          tz[r] = fmaf(w[r], dz[r], tz[r]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (KAHAN) {
+        float yv, t;
+        yv = tx[r] - cx[r]; t = sx[r] + yv; cx[r] = (t - sx[r]) - yv; sx[r] = t;
+        yv = ty[r] - cy[r]; t = sy[r] + yv; cy[r] = (t - sy[r]) - yv; sy[r] = t;
+        yv = tz[r] - cz[r]; t = sz[r] + yv; cz[r] = (t - sz[r]) - yv; sz[r] = t;
+      } else {
+        ax[r] += (double)tx[r];
+        ay[r] += (double)ty[r];
+        az[r] += (double)tz[r];
+      }
+    }
+  }
+
+  double *o = out + (size_t)blockIdx.y * 3 * (size_t)n;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = ibase + 64 * r;
+    if (i < n) {
+      if (KAHAN) {
+        o[i] = (double)sx[r] - (double)cx[r];
+        o[(size_t)n + i] = (double)sy[r] - (double)cy[r];
+        o[2 * (size_t)n + i] = (double)sz[r] - (double)cz[r];
+      } else {
+        o[i] = ax[r];
+        o[(size_t)n + i] = ay[r];
+        o[2 * (size_t)n + i] = az[r];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers and the variant table
+// ---------------------------------------------------------------------------
+inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+template <int R, int TJ, bool E2, bool CULL>
+hipError_t launch_f64(const ForceLaunch &L, hipStream_t s) {
+  dim3 grid(ceil_div(L.n, (long long)kBlock * R), L.jsplit);
+  hipLaunchKernelGGL((k_force_f64<R, TJ, E2, CULL>), grid, dim3(kBlock), 0, s,
+                     L.pos, L.mass, L.soft, L.n, L.jchunk, L.tinfo, L.out);
+  return hipGetLastError();
+}
+
+template <int R, int TJ, bool CULL>
+hipError_t launch_mixed(const ForceLaunch &L, hipStream_t s) {
+  dim3 grid(ceil_div(L.n, (long long)kBlock * R), L.jsplit);
+  if (L.kahan) {
+    hipLaunchKernelGGL((k_force_mixed<R, TJ, true, CULL>), grid, dim3(kBlock),
+                       0, s, L.shadow, L.n, L.jchunk, L.tinfo, L.out);
+  } else {
+    hipLaunchKernelGGL((k_force_mixed<R, TJ, false, CULL>), grid,
+                       dim3(kBlock), 0, s, L.shadow, L.n, L.jchunk, L.tinfo,
+                       L.out);
+  }
+  return hipGetLastError();
+}
+
+// variant bits: 1 = FP64 weight without the e^2 term; 2 = sorted input with
+// (wave, tile) culling of the softening test.
+#define F64_SET(R)                                                  \
+  {kClassF64, R, 128, 0, launch_f64<R, 128, true, false>},          \
+      {kClassF64, R, 128, 1, launch_f64<R, 128, false, false>},     \
+      {kClassF64, R, 128, 2, launch_f64<R, 128, true, true>},       \
+      {kClassF64, R, 128, 3, launch_f64<R, 128, false, true>}
+#define MIXED_SET(R, TJ)                                            \
+  {kClassMixed, R, TJ, 0, launch_mixed<R, TJ, false>},              \
+      {kClassMixed, R, TJ, 2, launch_mixed<R, TJ, true>}
+
+const ForceVariant kVariants[] = {
+    F64_SET(1),         F64_SET(2),         F64_SET(4),         F64_SET(8),
+    MIXED_SET(1, 128),  MIXED_SET(2, 256),  MIXED_SET(4, 256),  MIXED_SET(8, 256),
+};
+
+}  // namespace
+
+const ForceVariant *force_variants(int *count) {
+  *count = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
+  return kVariants;
+}
+
+const ForceVariant *find_force_variant(int cls, int r, int tj, int variant) {
+  for (const ForceVariant &v : kVariants) {
+    if (v.cls == cls && v.r == r && v.tj == tj && v.variant == variant) {
+      return &v;
+    }
+  }
+  return nullptr;
+}
+
+}  // namespace steps

@@ -24,7 +24,12 @@ struct ForceLaunch {
   int jsplit = 1;   // grid rows; > 1 writes partials
   double *out = nullptr;       // [jsplit][3][n] (or acc when jsplit == 1)
   int kahan = 0;               // mixed only: Kahan FP32 accumulation
+  const double *tinfo = nullptr;  // culled variants: [n/tj][8] tile boxes
 };
+
+// variant bits of a force kernel
+constexpr int kVarNoE2 = 1;  // FP64: r^-3 correction to first order only
+constexpr int kVarCull = 2;  // sorted input, (wave, tile) softening culling
 
 struct ForceVariant {
   int cls;   // PrecClass
@@ -37,6 +42,30 @@ struct ForceVariant {
 // All compiled force-kernel variants.
 const ForceVariant *force_variants(int *count);
 const ForceVariant *find_force_variant(int cls, int r, int tj, int variant);
+
+// ---- spatial sort for the culled variants (steps_sort.hip) -------------
+int bbox_blocks(int n);
+// box[6] = (lo xyz, hi xyz) of pos; part holds bbox_blocks(n) * 6 doubles
+hipError_t launch_bbox(const double *pos, int n, double *part, double *box,
+                       hipStream_t s);
+hipError_t launch_morton(const double *pos, int n, const double *box,
+                         unsigned long long *keys, int *vals, hipStream_t s);
+// stable radix sort of (key, index); tmp == nullptr queries *tmp_bytes
+hipError_t sort_pairs(void *tmp, size_t *tmp_bytes,
+                      const unsigned long long *kin, unsigned long long *kout,
+                      const int *vin, int *vout, int n, hipStream_t s);
+// sorted [5][n] FP64 copy (x, y, z, m, h) and/or FP32 shadow (may be null)
+hipError_t launch_gather(const double *pos, const double *mass,
+                         const double *soft, const int *perm, int n,
+                         double *sorted, float *shadow, hipStream_t s);
+// per tile of tj sorted particles: (lo xyz, hi xyz, hmax, 0)
+hipError_t launch_tile_info_f64(const double *sorted, int n, int tj,
+                                double *info, hipStream_t s);
+hipError_t launch_tile_info_f32(const float *shadow, int n, int tj,
+                                double *info, hipStream_t s);
+// acc[d][perm[k]] = sum over the jsplit partials [jsplit][3][n]
+hipError_t launch_reduce_scatter(const double *part, int jsplit, int n,
+                                 const int *perm, double *acc, hipStream_t s);
 
 // Sum jsplit partials [jsplit][3][n] into acc [3][n] in fixed order.
 hipError_t launch_reduce_partials(const double *part, int jsplit, int n,

@@ -70,16 +70,15 @@ def _variants(st):
     out = []
     for prec in ("fp64", "mixed", "kahan"):
         ctx = st.Context(0, precision=prec)
-        for r, tj, var in {(1, 128, 0), (2, 128, 0), (4, 128, 0), (4, 256, 0),
-                           (8, 128, 0), (1, 128, 1), (2, 128, 1), (4, 128, 1),
-                           (4, 256, 1), (8, 128, 1), (2, 256, 0),
-                           (8, 256, 0)}:
-            for js in (1, 3, 7):
-                try:
-                    ctx.set_tile(r, tj, js, var)
-                except st.StepsError:
-                    continue
-                out.append((prec, r, tj, var, js))
+        for r in (1, 2, 4, 8):
+            for tj in (128, 256):
+                for var in (0, 1, 2, 3):
+                    for js in (1, 3, 7):
+                        try:
+                            ctx.set_tile(r, tj, js, var)
+                        except st.StepsError:
+                            continue
+                        out.append((prec, r, tj, var, js))
         ctx.close()
     return out
 
@@ -89,7 +88,8 @@ def test_every_launch_shape(st):
     pos, mass, soft = clustered(1537, 23, 0.1)
     ref = oracle.forces(pos, mass, soft)
     shapes = _variants(st)
-    assert len(shapes) >= 3 * 14
+    # FP64: 4 r x 4 variants; mixed, Kahan: 4 r x 2 variants; 3 splits each
+    assert len(shapes) == (16 + 8 + 8) * 3
     ctxs = {p: st.Context(0, precision=p) for p in ("fp64", "mixed", "kahan")}
     for prec, r, tj, var, js in shapes:
         ctx = ctxs[prec]
