@@ -200,19 +200,19 @@ def profiled_traffic(precision, tile, workload):
     source has changed since it was taken."""
     import hashlib
     cls = "f64" if precision == "fp64" else "mixed"
-    tag = "e2" if tile["variant"] == 0 else "e1"
-    path = os.path.join(ROOT, "profiles", "k_force_%s_r%d_tj%d_%s_workload%d.md"
-                        % (cls, tile["r"], tile["tj"], tag, workload))
+    path = os.path.join(ROOT, "profiles", "k_force_%s_r%d_tj%d_v%d_workload%d.md"
+                        % (cls, tile["r"], tile["tj"], tile["variant"], workload))
     if not os.path.exists(path):
         return None
-    src = os.path.join(ROOT, "paper_1811_05903_amd", "csrc", "steps_kernels.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     traffic, ok = None, False
     for line in open(path):
         if line.startswith("traffic_bytes_per_launch:"):
             traffic = float(line.split(":", 1)[1])
         if line.startswith("source_sha256:"):
-            ok = line.split(":", 1)[1].split()[0] == digest
+            digest, name = line.split(":", 1)[1].split()[:2]
+            src = os.path.join(ROOT, "paper_1811_05903_amd", "csrc", name.strip("()"))
+            ok = (os.path.exists(src) and
+                  hashlib.sha256(open(src, "rb").read()).hexdigest() == digest)
     return traffic if ok else None
 
 
