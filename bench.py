@@ -47,6 +47,9 @@ def parse():
                     choices=["fp64", "mixed", "kahan"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-member ensemble comparison")
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -181,6 +184,8 @@ def main():
             bidx = np.sort(np.random.default_rng(3).choice(big.n, 32, replace=False))
             big_rows = (bidx, oracle.forces(big.pos, big.mass, big.soft, idx=bidx))
         out["modes_n2e21"] = mode_table(st, big, big_rows, dev)
+    if not args.no_batch:
+        out["batch"] = batch_leg(st, dev, args.batch_steps)
     ctx.close()
     if args.copy_calibration:
         nb = args.copy_calibration << 20
@@ -214,6 +219,65 @@ def profiled_traffic(precision, tile, workload):
             ok = (os.path.exists(src) and
                   hashlib.sha256(open(src, "rb").read()).hexdigest() == digest)
     return traffic if ok else None
+
+
+def batch_leg(st, dev, nsteps):
+    """Workload 4: 64 members, N_b ~ U{8192..131072}, Omega_m ~ U[0.25,
+    0.35] flat, 100 log steps a 0.02 -> 1.0, mixed precision: one
+    steps_batch_run (persistent kernel, graph-replayed step, autotuned)
+    against the same members run one after another with steps_step."""
+    import numpy as np
+    import torch
+    import synth
+    members = synth.ensemble(nsteps=nsteps)
+    offs = np.cumsum([0] + [m.n for m in members])
+    cat = lambda key, axis: np.ascontiguousarray(
+        np.concatenate([getattr(m, key) for m in members], axis=axis))
+    cos = [st.Cosmology(m.cosmo.H0, m.cosmo.omega_m, m.cosmo.omega_l)
+           for m in members]
+    a0 = [m.a0 for m in members]
+    a1 = [m.a1 for m in members]
+    pairs = float(sum(m.n * m.n for m in members)) * nsteps
+    ctx = st.Context(0, precision="mixed")
+    flags = st.STEPS_BATCH_GRAPH | st.STEPS_BATCH_AUTOTUNE
+    mass, soft = dev(cat("mass", 0)), dev(cat("soft", 0))
+    # warm-up run (allocations, code objects), 2 steps
+    p, v = dev(cat("pos", 1)), dev(cat("vel", 1))
+    acc = torch.zeros_like(p)
+    st.steps_batch_run(p, v, mass, soft, acc, offs, cos, a0, a1, 2,
+                       flags=flags, ctx=ctx)
+    p, v = dev(cat("pos", 1)), dev(cat("vel", 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status = st.steps_batch_run(p, v, mass, soft, acc, offs, cos, a0, a1,
+                                nsteps, flags=flags, ctx=ctx)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    tile = st.steps_batch_tile(ctx)
+    log("ensemble: %d members, N=%d, %d steps batched in %.2f s (%.3e pairs/s), tile %s"
+        % (len(members), offs[-1], nsteps, t_batch, pairs / t_batch, tile))
+    # sequential: each member alone through steps_step
+    per = [(dev(m.pos), dev(m.vel), dev(m.mass), dev(m.soft)) for m in members]
+    grids = [m.a_grid() for m in members]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for (pp, vv, mm, hh), g, c in zip(per, grids, cos):
+        aa = st.steps_forces(pp, mm, hh, ctx=ctx)
+        for k in range(nsteps):
+            st.steps_step(pp, vv, mm, hh, aa, g[k], g[k + 1] - g[k], c, ctx=ctx)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    log("ensemble: sequential steps_step runs %.2f s (%.3e pairs/s); batched %.2fx"
+        % (t_seq, pairs / t_seq, t_seq / t_batch))
+    ctx.close()
+    return {"members": len(members), "n_total": int(offs[-1]),
+            "steps": nsteps, "pairs_per_step": pairs / nsteps,
+            "precision": "mixed_f64acc", "status_ok": status.count(0),
+            "batched_s": t_batch, "batched_pairs_per_s": pairs / t_batch,
+            "sequential_s": t_seq, "sequential_pairs_per_s": pairs / t_seq,
+            "speedup": t_seq / t_batch, "tile": tile,
+            "note": "batched time includes the in-library sort, autotune "
+                    "and initial force evaluation"}
 
 
 def mode_table(st, ps, rows, dev):

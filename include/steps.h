@@ -188,6 +188,56 @@ int steps_step(double *pos, double *vel, const double *mass,
                const double *soft, int64_t n, double *acc, double a,
                double da, const steps_cosmology *cosmo);
 
+/* ---- ensembles of independent simulations ------------------------------ */
+/* The paper motivates fast simulations for fitting cosmological parameters
+ * (abstract); an ensemble runs many small, independent StePS simulations of
+ * uneven size and cosmology together.  Pairs interact only within their
+ * own member. */
+
+/* Capture one step (kick+drift, pair sum, kick) as a hipGraph and replay
+ * it; without the flag the same kernels are launched one by one (the two
+ * give bitwise identical results). */
+#define STEPS_BATCH_GRAPH 1u
+/* Before stepping, time each compiled ensemble kernel on the first force
+ * evaluation and keep the fastest (steps_batch_tile reports it). */
+#define STEPS_BATCH_AUTOTUNE 2u
+
+typedef struct steps_batch {
+  int32_t members;          /* B >= 1 */
+  int32_t nsteps;           /* KDK steps per member, >= 1 */
+  const int64_t *offsets;   /* HOST [B + 1]: offsets[0] = 0, nondecreasing;
+                               member b owns columns [offsets[b],
+                               offsets[b+1]) of the arena */
+  double *pos;              /* device [3][N], N = offsets[B]; in/out */
+  double *vel;              /* device [3][N]; in/out */
+  const double *mass;       /* device [N] */
+  const double *soft;       /* device [N] */
+  double *acc;              /* device [3][N]; out: S(final pos) per member */
+  const steps_cosmology *cosmo; /* HOST [B] */
+  const double *a0;         /* HOST [B]: start scale factor (> 0) */
+  const double *a1;         /* HOST [B]: end scale factor (> 0) */
+  uint32_t flags;           /* STEPS_BATCH_GRAPH | STEPS_BATCH_AUTOTUNE */
+  int32_t resort_every;     /* refresh the internal spatial order every k
+                               steps; 0 = order once at the start */
+} steps_batch;
+
+/* Run every member nsteps KDK steps (as steps_step) on the log-uniform grid
+ * a_k = a0 (a1/a0)^(k/nsteps), k = 0..nsteps, in the context's precision.
+ * The forces of the initial positions are computed first (acc is output
+ * only).  Internally the ensemble is held in one arena in spatial (Morton)
+ * order within each member; one persistent kernel launch per step sums all
+ * members, its blocks pulling (member, i-block) items longest first from an
+ * atomic counter.  Synchronous: returns when the run is complete.
+ * member_status (HOST [B], may be NULL) receives per member STEPS_OK or the
+ * reason it was skipped (bad cosmology, a0/a1, or H^2 <= 0 on its grid);
+ * skipped members' columns are left untouched and do not stop the others.
+ * Errors for the whole call: null or invalid pointers, B < 1, nsteps < 1,
+ * non-monotone offsets, N > 2^30, overlapping arrays, unknown flags. */
+int steps_batch_run(steps_ctx *ctx, const steps_batch *batch,
+                    int32_t *member_status);
+/* Launch shape of the last steps_batch_run on this context. */
+int steps_batch_tile(steps_ctx *ctx, steps_tile *out);
+
 /* ---- background helpers (host only, no device work) ------------------- */
 /* H(a) in 1/Gyr (Eq. 1). */
 int steps_hubble(const steps_cosmology *cosmo, double a, double *out);

@@ -54,9 +54,12 @@ EXPORTS = (
     "steps_ctx_set_flags", "steps_ctx_set_tile", "steps_ctx_get_tile",
     "steps_sync", "steps_ctx_force_timing", "steps_forces_ctx",
     "steps_forces", "steps_potential_ctx", "steps_potential",
-    "steps_step_ctx", "steps_step", "steps_hubble", "steps_dt", "steps_G",
-    "steps_kms_to_mpc_per_gyr",
+    "steps_step_ctx", "steps_step", "steps_batch_run", "steps_batch_tile",
+    "steps_hubble", "steps_dt", "steps_G", "steps_kms_to_mpc_per_gyr",
 )
+
+STEPS_BATCH_GRAPH = 1
+STEPS_BATCH_AUTOTUNE = 2
 
 
 class StepsError(RuntimeError):
@@ -70,6 +73,18 @@ class steps_cosmology(ctypes.Structure):
                 ("omega_l", ctypes.c_double), ("omega_r", ctypes.c_double),
                 ("omega_k", ctypes.c_double), ("G", ctypes.c_double),
                 ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class steps_batch(ctypes.Structure):
+    _fields_ = [("members", ctypes.c_int32), ("nsteps", ctypes.c_int32),
+                ("offsets", ctypes.POINTER(ctypes.c_int64)),
+                ("pos", ctypes.c_void_p), ("vel", ctypes.c_void_p),
+                ("mass", ctypes.c_void_p), ("soft", ctypes.c_void_p),
+                ("acc", ctypes.c_void_p),
+                ("cosmo", ctypes.POINTER(steps_cosmology)),
+                ("a0", ctypes.POINTER(ctypes.c_double)),
+                ("a1", ctypes.POINTER(ctypes.c_double)),
+                ("flags", ctypes.c_uint32), ("resort_every", ctypes.c_int32)]
 
 
 class steps_tile(ctypes.Structure):
@@ -138,6 +153,9 @@ def load():
             "steps_potential": ([vp, vp, vp, i64, vp], i32),
             "steps_step_ctx": ([vp, vp, vp, vp, vp, i64, vp, d, d, pc], i32),
             "steps_step": ([vp, vp, vp, vp, i64, vp, d, d, pc], i32),
+            "steps_batch_run": ([vp, ctypes.POINTER(steps_batch),
+                                 ctypes.POINTER(ctypes.c_int32)], i32),
+            "steps_batch_tile": ([vp, pt], i32),
             "steps_hubble": ([pc, d, ctypes.POINTER(d)], i32),
             "steps_dt": ([pc, d, d, ctypes.POINTER(d)], i32),
             "steps_G": ([], d),
@@ -336,3 +354,34 @@ def run(pos, vel, mass, soft, a_grid, cosmo: Cosmology, ctx=None, acc=None):
         steps_step(pos, vel, mass, soft, acc, a_grid[k],
                    a_grid[k + 1] - a_grid[k], cosmo, ctx=ctx)
     return acc
+
+
+def steps_batch_run(pos, vel, mass, soft, acc, offsets, cosmos, a0, a1,
+                    nsteps, flags=0, resort_every=0, ctx: Context | None = None):
+    """Run an ensemble (see steps.h): arena tensors pos/vel/acc (3, N),
+    mass/soft (N,), member b = columns offsets[b]:offsets[b+1].  cosmos, a0,
+    a1 are per-member Python sequences.  Returns the per-member status
+    codes (0 = ran).  Synchronous."""
+    B = len(cosmos)
+    if len(offsets) != B + 1 or len(a0) != B or len(a1) != B:
+        raise ValueError("offsets must have members + 1 entries, a0/a1 members")
+    n = int(offsets[-1])
+    c = ctx or default_context(pos.device.index or 0)
+    offs = (ctypes.c_int64 * (B + 1))(*[int(x) for x in offsets])
+    cs = (steps_cosmology * B)(*[k.to_c() for k in cosmos])
+    a0s = (ctypes.c_double * B)(*[float(x) for x in a0])
+    a1s = (ctypes.c_double * B)(*[float(x) for x in a1])
+    b = steps_batch(B, int(nsteps), offs, _dev(pos, "pos", (3, n)),
+                    _dev(vel, "vel", (3, n)), _dev(mass, "mass", (n,)),
+                    _dev(soft, "soft", (n,)), _dev(acc, "acc", (3, n)), cs,
+                    a0s, a1s, int(flags), int(resort_every))
+    status = (ctypes.c_int32 * B)()
+    c.bind_stream()
+    _check(c._lib.steps_batch_run(c.handle, ctypes.byref(b), status))
+    return list(status)
+
+
+def steps_batch_tile(ctx: Context):
+    t = steps_tile()
+    _check(ctx._lib.steps_batch_tile(ctx.handle, ctypes.byref(t)))
+    return {"r": t.r, "tj": t.tj, "jsplit": t.jsplit, "variant": t.variant}

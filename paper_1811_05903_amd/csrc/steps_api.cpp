@@ -75,6 +75,7 @@ struct steps_ctx {
   Buffer part;     // j-split partial sums
   Buffer shadow;   // FP32 shadow of the inputs
   Buffer arena;    // spatial-sort scratch (keys, permutation, sorted copy)
+  steps_tile batch_tile = {0, 0, 0, 0};  // shape of the last ensemble run
   int *flag = nullptr;  // device int for the finite check
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
   std::vector<hipEvent_t> prof_pool;
@@ -732,6 +733,495 @@ int steps_step(double *pos, double *vel, const double *mass,
   steps_ctx *c = default_ctx(&rc);
   if (!c) return rc;
   return steps_step_ctx(c, pos, vel, mass, soft, n, acc, a, da, cosmo);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Ensembles
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchLayout {
+  std::vector<int> tile_beg, tile_end;   // member-local tiles, slot ranges
+  std::vector<int4> items;               // (i0, iend, jbeg, jend)
+  std::vector<int> tbase;                // first tile of the item's member
+};
+
+// Tiles of tj slots from each member's start; items of 256 r slots, ordered
+// by member size (the cost of an item), largest first.
+BatchLayout batch_layout(const std::vector<int> &soff, int r, int tj) {
+  BatchLayout L;
+  const int A = (int)soff.size() - 1;
+  std::vector<int> mtb(A);
+  for (int a = 0; a < A; ++a) {
+    mtb[a] = (int)L.tile_beg.size();
+    for (int k = soff[a]; k < soff[a + 1]; k += tj) {
+      L.tile_beg.push_back(k);
+      L.tile_end.push_back(std::min(k + tj, soff[a + 1]));
+    }
+  }
+  std::vector<int> order(A);
+  for (int a = 0; a < A; ++a) order[a] = a;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return soff[x + 1] - soff[x] > soff[y + 1] - soff[y];
+  });
+  for (int a : order) {
+    for (int i0 = soff[a]; i0 < soff[a + 1]; i0 += 256 * r) {
+      L.items.push_back(make_int4(i0, std::min(i0 + 256 * r, soff[a + 1]),
+                                  soff[a], soff[a + 1]));
+      L.tbase.push_back(mtb[a]);
+    }
+  }
+  return L;
+}
+
+// Everything one ensemble run keeps on the device (carved from the arena).
+struct BatchDev {
+  double *pos, *vel, *acc, *mass, *soft;  // sorted state, [.][N]
+  double *tpos, *tvel, *tacc, *tmass, *tsoft;  // re-sort staging
+  int *orig, *torig, *mid;
+  unsigned long long *k0, *k1;
+  int *v0, *v1;
+  void *cub;
+  size_t cub_bytes;
+  float *shadow;
+  double *info, *table, *bpart, *box;
+  int *tile_beg, *tile_end, *tbase, *counter;
+  int4 *items;
+};
+
+struct BatchRun {
+  steps_ctx *c;
+  hipStream_t s;
+  int N, A, nsteps, cls, kahan;
+  BatchDev d;
+  const steps::BatchVariant *v = nullptr;
+  int ntiles = 0, nitems = 0;
+};
+
+hipError_t batch_forces(BatchRun &R) {
+  hipError_t e;
+  if (R.cls == steps::kClassF64) {
+    e = steps::launch_batch_tile_info_f64(R.d.pos, R.N, R.d.tile_beg,
+                                          R.d.tile_end, R.ntiles, R.d.info,
+                                          R.s);
+  } else {
+    e = steps::launch_batch_tile_info_f32(R.d.shadow, R.N, R.d.tile_beg,
+                                          R.d.tile_end, R.ntiles, R.d.info,
+                                          R.s);
+  }
+  if (e != hipSuccess) return e;
+  steps::BatchLaunch L;
+  L.pos = R.d.pos;
+  L.mass = R.d.mass;
+  L.soft = R.d.soft;
+  L.shadow = R.d.shadow;
+  L.stride = R.N;
+  L.items = R.d.items;
+  L.tbase = R.d.tbase;
+  L.nitems = R.nitems;
+  L.tinfo = R.d.info;
+  L.out = R.d.acc;
+  L.counter = R.d.counter + 1;
+  L.kahan = R.kahan;
+  return R.v->launch(L, R.s);
+}
+
+// One KDK step; only kernel launches (capturable).
+hipError_t batch_step(BatchRun &R) {
+  hipError_t e = steps::launch_batch_kick_drift(
+      R.d.pos, R.d.vel, R.d.acc, R.cls == steps::kClassMixed ? R.d.shadow : nullptr,
+      R.d.mid, R.N, R.d.table, R.A, R.nsteps, R.d.counter, R.s);
+  if (e == hipSuccess) e = batch_forces(R);
+  if (e == hipSuccess) {
+    e = steps::launch_batch_kick_end(R.d.pos, R.d.vel, R.d.acc, R.d.mid, R.N,
+                                     R.d.table, R.A, R.nsteps, R.d.counter, R.s);
+  }
+  if (e == hipSuccess) e = steps::launch_batch_advance(R.d.counter, R.s);
+  return e;
+}
+
+// Morton order within each member (member index in the key's high bits).
+hipError_t batch_resort(BatchRun &R) {
+  int mbits = 1;
+  while ((1 << mbits) < R.A) ++mbits;
+  const int qbits = std::min(21, (63 - mbits) / 3);
+  hipError_t e = steps::launch_bbox(R.d.pos, R.N, R.d.bpart, R.d.box, R.s);
+  if (e == hipSuccess) {
+    e = steps::launch_batch_morton(R.d.pos, R.N, R.d.box, R.d.mid, qbits,
+                                   R.d.k0, R.d.v0, R.s);
+  }
+  if (e == hipSuccess) {
+    e = steps::sort_pairs(R.d.cub, &R.d.cub_bytes, R.d.k0, R.d.k1, R.d.v0,
+                          R.d.v1, R.N, R.s);
+  }
+  const int *perm = R.d.v1;
+  struct {
+    double *a, *t;
+    int comps;
+  } cols[5] = {{R.d.pos, R.d.tpos, 3}, {R.d.vel, R.d.tvel, 3},
+               {R.d.acc, R.d.tacc, 3}, {R.d.mass, R.d.tmass, 1},
+               {R.d.soft, R.d.tsoft, 1}};
+  for (auto &c : cols) {
+    if (e != hipSuccess) break;
+    e = steps::launch_gather_cols(c.a, R.N, perm, R.N, c.t, R.N, c.comps, R.s);
+    if (e == hipSuccess) {
+      e = hipMemcpyAsync(c.a, c.t, (size_t)c.comps * R.N * sizeof(double),
+                         hipMemcpyDeviceToDevice, R.s);
+    }
+  }
+  if (e == hipSuccess) e = steps::launch_gather_int(R.d.orig, perm, R.N, R.d.torig, R.s);
+  if (e == hipSuccess) {
+    e = hipMemcpyAsync(R.d.orig, R.d.torig, (size_t)R.N * sizeof(int),
+                       hipMemcpyDeviceToDevice, R.s);
+  }
+  if (e == hipSuccess && R.cls == steps::kClassMixed) {
+    e = steps::launch_shadow(R.d.pos, R.d.mass, R.d.soft, R.N, R.d.shadow, R.s);
+  }
+  return e;
+}
+
+hipError_t upload_layout(BatchRun &R, const BatchLayout &L) {
+  R.ntiles = (int)L.tile_beg.size();
+  R.nitems = (int)L.items.size();
+  hipError_t e = hipMemcpyAsync(R.d.tile_beg, L.tile_beg.data(),
+                                L.tile_beg.size() * sizeof(int),
+                                hipMemcpyHostToDevice, R.s);
+  if (e == hipSuccess) {
+    e = hipMemcpyAsync(R.d.tile_end, L.tile_end.data(),
+                       L.tile_end.size() * sizeof(int), hipMemcpyHostToDevice,
+                       R.s);
+  }
+  if (e == hipSuccess) {
+    e = hipMemcpyAsync(R.d.items, L.items.data(), L.items.size() * sizeof(int4),
+                       hipMemcpyHostToDevice, R.s);
+  }
+  if (e == hipSuccess) {
+    e = hipMemcpyAsync(R.d.tbase, L.tbase.data(), L.tbase.size() * sizeof(int),
+                       hipMemcpyHostToDevice, R.s);
+  }
+  // the host vectors must outlive the copies
+  if (e == hipSuccess) e = hipStreamSynchronize(R.s);
+  return e;
+}
+
+// Validate one member and fill its rows of the step table; returns a
+// STEPS_E_* code (the member is then skipped) or STEPS_OK.
+int batch_member(const steps_cosmology *k, double a0, double a1, int nsteps,
+                 int A, int a, std::vector<double> &table) {
+  if (validate_cosmo(k) != STEPS_OK) return STEPS_E_INVAL;
+  const bool newton = k->mode == STEPS_NEWTONIAN_TEST;
+  // the log-uniform grid needs a0, a1 > 0 in both modes
+  if (!std::isfinite(a0) || !std::isfinite(a1) || a0 <= 0.0 || a1 <= 0.0) {
+    return STEPS_E_INVAL;
+  }
+  const steps::Background bg = make_background(k);
+  const double lr = std::log(a1 / a0);
+  double ak = a0;
+  for (int s = 0; s < nsteps; ++s) {
+    const double an = s + 1 == nsteps ? a1 : a0 * std::exp(lr * (s + 1) / nsteps);
+    double dt = 0.0;
+    if (!bg.step_dt(ak, an - ak, &dt) || !std::isfinite(dt)) return STEPS_E_INVAL;
+    const double hdt = 0.5 * dt;
+    const double i0 = newton ? 1.0 : 1.0 / (ak * ak * ak);
+    const double i1 = newton ? 1.0 : 1.0 / (an * an * an);
+    const double den = 1.0 + 2.0 * bg.hubble(an) * hdt;
+    if (!(den > 0.0)) return STEPS_E_INVAL;
+    double *t = &table[((size_t)s * A + a) * steps::kBatchScalars];
+    t[0] = hdt;
+    t[1] = bg.g * i0;
+    t[2] = bg.radial() * i0;
+    t[3] = 2.0 * bg.hubble(ak);
+    t[4] = dt;
+    t[5] = bg.g * i1;
+    t[6] = bg.radial() * i1;
+    t[7] = 1.0 / den;
+    ak = an;
+  }
+  return STEPS_OK;
+}
+
+int batch_fail_cleanup(int rc, hipStream_t s, hipGraph_t g, hipGraphExec_t x) {
+  if (x) (void)hipGraphExecDestroy(x);
+  if (g) (void)hipGraphDestroy(g);
+  if (s) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int steps_batch_tile(steps_ctx *c, steps_tile *out) {
+  if (!c || !out) return fail(STEPS_E_INVAL, "ctx or out is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  *out = c->batch_tile;
+  return STEPS_OK;
+}
+
+int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
+  if (!c || !b) return fail(STEPS_E_INVAL, "ctx or batch is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  const int B = b->members;
+  if (B < 1) return fail(STEPS_E_INVAL, "members must be >= 1");
+  if (b->nsteps < 1) return fail(STEPS_E_INVAL, "nsteps must be >= 1");
+  if (!b->offsets || !b->cosmo || !b->a0 || !b->a1) {
+    return fail(STEPS_E_INVAL, "offsets, cosmo, a0 and a1 must be host arrays");
+  }
+  if (b->flags & ~(STEPS_BATCH_GRAPH | STEPS_BATCH_AUTOTUNE)) {
+    return fail(STEPS_E_INVAL, "unknown batch flag bits 0x%x", b->flags);
+  }
+  if (b->resort_every < 0) return fail(STEPS_E_INVAL, "resort_every < 0");
+  if (b->offsets[0] != 0) return fail(STEPS_E_INVAL, "offsets[0] != 0");
+  for (int m = 0; m < B; ++m) {
+    if (b->offsets[m + 1] < b->offsets[m]) {
+      return fail(STEPS_E_INVAL, "offsets decrease at member %d", m);
+    }
+  }
+  const int64_t Nc = b->offsets[B];
+  int rc = check_n(Nc);
+  if (rc) return rc;
+  const int nsteps = b->nsteps;
+
+  // per-member validation and step tables (active members only)
+  std::vector<int32_t> st(B, STEPS_OK);
+  std::vector<int> active;
+  std::vector<double> table_all((size_t)nsteps * B * steps::kBatchScalars, 0.0);
+  for (int m = 0; m < B; ++m) {
+    st[m] = batch_member(&b->cosmo[m], b->a0[m], b->a1[m], nsteps, B, m,
+                         table_all);
+    if (st[m] == STEPS_OK && b->offsets[m + 1] > b->offsets[m]) active.push_back(m);
+  }
+  auto write_status = [&]() {
+    if (status) {
+      for (int m = 0; m < B; ++m) status[m] = st[m];
+    }
+  };
+  if (active.empty()) {
+    write_status();
+    return STEPS_OK;
+  }
+  const size_t v3 = 3 * (size_t)Nc * sizeof(double), v1 = (size_t)Nc * sizeof(double);
+  if ((rc = check_ptr(c, b->pos, v3, "batch.pos"))) return rc;
+  if ((rc = check_ptr(c, b->vel, v3, "batch.vel"))) return rc;
+  if ((rc = check_ptr(c, b->acc, v3, "batch.acc"))) return rc;
+  if ((rc = check_ptr(c, b->mass, v1, "batch.mass"))) return rc;
+  if ((rc = check_ptr(c, b->soft, v1, "batch.soft"))) return rc;
+  const void *rw[3] = {b->pos, b->vel, b->acc};
+  for (int x = 0; x < 3; ++x) {
+    if (overlap(rw[x], v3, b->mass, v1) || overlap(rw[x], v3, b->soft, v1)) {
+      return fail(STEPS_E_INVAL, "batch pos/vel/acc overlap mass or soft");
+    }
+    for (int y = x + 1; y < 3; ++y) {
+      if (overlap(rw[x], v3, rw[y], v3)) {
+        return fail(STEPS_E_INVAL, "batch pos, vel and acc must not overlap");
+      }
+    }
+  }
+
+  // slot layout of the active members
+  const int A = (int)active.size();
+  std::vector<int> soff(A + 1, 0), orig, mid;
+  for (int a = 0; a < A; ++a) {
+    const int m = active[a];
+    soff[a + 1] = soff[a] + (int)(b->offsets[m + 1] - b->offsets[m]);
+    for (int64_t i = b->offsets[m]; i < b->offsets[m + 1]; ++i) {
+      orig.push_back((int)i);
+      mid.push_back(a);
+    }
+  }
+  const int N = soff[A];
+  std::vector<double> table((size_t)nsteps * A * steps::kBatchScalars);
+  for (int s = 0; s < nsteps; ++s) {
+    for (int a = 0; a < A; ++a) {
+      std::copy_n(&table_all[((size_t)s * B + active[a]) * steps::kBatchScalars],
+                  steps::kBatchScalars,
+                  &table[((size_t)s * A + a) * steps::kBatchScalars]);
+    }
+  }
+
+  // kernel candidates of this precision
+  BatchRun R;
+  R.c = c;
+  R.N = N;
+  R.A = A;
+  R.nsteps = nsteps;
+  R.cls = prec_class(c->precision);
+  R.kahan = c->precision == STEPS_MIXED_KAHAN;
+  std::vector<const steps::BatchVariant *> cands;
+  {
+    int cnt = 0;
+    const steps::BatchVariant *bv = steps::batch_variants(&cnt);
+    for (int k = 0; k < cnt; ++k) {
+      if (bv[k].cls == R.cls) cands.push_back(&bv[k]);
+    }
+  }
+  // default: FP64 r=4 without the e^2 term, mixed r=2 (the single-run tuning)
+  for (const auto *v : cands) {
+    const bool want = R.cls == steps::kClassF64 ? (v->r == 4 && v->variant == 3)
+                                                : v->r == 2;
+    if (want) R.v = v;
+  }
+  if (!R.v) R.v = cands.front();
+
+  // device memory
+  size_t cub_bytes = 0;
+  hipError_t e = steps::sort_pairs(nullptr, &cub_bytes, nullptr, nullptr,
+                                   nullptr, nullptr, N, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "radix sort size query");
+  const size_t max_tiles = (size_t)N / 128 + A + 1;
+  const size_t max_items = (size_t)N / 256 + A + 1;
+  const size_t n = (size_t)N, d8 = sizeof(double);
+  Carve cv;
+  const size_t o_pos = cv.take(3 * n * d8), o_vel = cv.take(3 * n * d8),
+               o_acc = cv.take(3 * n * d8), o_mass = cv.take(n * d8),
+               o_soft = cv.take(n * d8), o_tpos = cv.take(3 * n * d8),
+               o_tvel = cv.take(3 * n * d8), o_tacc = cv.take(3 * n * d8),
+               o_tmass = cv.take(n * d8), o_tsoft = cv.take(n * d8),
+               o_orig = cv.take(n * 4), o_torig = cv.take(n * 4),
+               o_mid = cv.take(n * 4), o_k0 = cv.take(n * 8),
+               o_k1 = cv.take(n * 8), o_v0 = cv.take(n * 4),
+               o_v1 = cv.take(n * 4), o_cub = cv.take(cub_bytes),
+               o_shadow = cv.take(R.cls == steps::kClassMixed ? 5 * n * 4 : 0),
+               o_info = cv.take(max_tiles * 8 * d8),
+               o_table = cv.take(table.size() * d8),
+               o_bpart = cv.take((size_t)steps::bbox_blocks(N) * 6 * d8),
+               o_box = cv.take(6 * d8), o_tb = cv.take(max_tiles * 4),
+               o_te = cv.take(max_tiles * 4), o_tbase = cv.take(max_items * 4),
+               o_items = cv.take(max_items * sizeof(int4)),
+               o_cnt = cv.take(2 * 4);
+  if ((rc = ensure(c, c->arena, cv.off, "ensemble"))) return rc;
+  char *base = (char *)c->arena.p;
+  BatchDev &d = R.d;
+  d.pos = (double *)(base + o_pos);
+  d.vel = (double *)(base + o_vel);
+  d.acc = (double *)(base + o_acc);
+  d.mass = (double *)(base + o_mass);
+  d.soft = (double *)(base + o_soft);
+  d.tpos = (double *)(base + o_tpos);
+  d.tvel = (double *)(base + o_tvel);
+  d.tacc = (double *)(base + o_tacc);
+  d.tmass = (double *)(base + o_tmass);
+  d.tsoft = (double *)(base + o_tsoft);
+  d.orig = (int *)(base + o_orig);
+  d.torig = (int *)(base + o_torig);
+  d.mid = (int *)(base + o_mid);
+  d.k0 = (unsigned long long *)(base + o_k0);
+  d.k1 = (unsigned long long *)(base + o_k1);
+  d.v0 = (int *)(base + o_v0);
+  d.v1 = (int *)(base + o_v1);
+  d.cub = base + o_cub;
+  d.cub_bytes = cub_bytes;
+  d.shadow = R.cls == steps::kClassMixed ? (float *)(base + o_shadow) : nullptr;
+  d.info = (double *)(base + o_info);
+  d.table = (double *)(base + o_table);
+  d.bpart = (double *)(base + o_bpart);
+  d.box = (double *)(base + o_box);
+  d.tile_beg = (int *)(base + o_tb);
+  d.tile_end = (int *)(base + o_te);
+  d.tbase = (int *)(base + o_tbase);
+  d.items = (int4 *)(base + o_items);
+  d.counter = (int *)(base + o_cnt);
+
+  // the run uses its own stream (graph capture needs one), ordered after
+  // the context's earlier work
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  hipStream_t s = nullptr;
+  e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  R.s = s;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+#define BATCH_TRY(expr, what)                                              \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess) {                                                \
+      return batch_fail_cleanup(hip_fail(e_, what), s, graph, exec);       \
+    }                                                                      \
+  } while (0)
+
+  BATCH_TRY(hipMemcpyAsync(d.orig, orig.data(), n * sizeof(int),
+                           hipMemcpyHostToDevice, s), "upload");
+  BATCH_TRY(hipMemcpyAsync(d.mid, mid.data(), n * sizeof(int),
+                           hipMemcpyHostToDevice, s), "upload");
+  BATCH_TRY(hipMemcpyAsync(d.table, table.data(), table.size() * d8,
+                           hipMemcpyHostToDevice, s), "upload");
+  BATCH_TRY(steps::launch_gather_cols(b->pos, (int)Nc, d.orig, N, d.pos, N, 3, s), "gather");
+  BATCH_TRY(steps::launch_gather_cols(b->vel, (int)Nc, d.orig, N, d.vel, N, 3, s), "gather");
+  BATCH_TRY(steps::launch_gather_cols(b->mass, (int)Nc, d.orig, N, d.mass, N, 1, s), "gather");
+  BATCH_TRY(steps::launch_gather_cols(b->soft, (int)Nc, d.orig, N, d.soft, N, 1, s), "gather");
+  BATCH_TRY(hipStreamSynchronize(s), "upload");  // host vectors outlive the copies
+  BATCH_TRY(batch_resort(R), "ensemble sort");
+
+  // first forces, optionally timing every candidate kernel
+  if ((b->flags & STEPS_BATCH_AUTOTUNE) && cands.size() > 1) {
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    BATCH_TRY(hipEventCreate(&t0), "hipEventCreate");
+    BATCH_TRY(hipEventCreate(&t1), "hipEventCreate");
+    float best = 0.0f;
+    const steps::BatchVariant *win = nullptr;
+    for (const auto *v : cands) {
+      R.v = v;
+      BATCH_TRY(upload_layout(R, batch_layout(soff, v->r, v->tj)), "layout");
+      BATCH_TRY(steps::launch_batch_init(d.counter, s), "init");
+      BATCH_TRY(hipEventRecord(t0, s), "hipEventRecord");
+      BATCH_TRY(batch_forces(R), "ensemble force");
+      BATCH_TRY(hipEventRecord(t1, s), "hipEventRecord");
+      BATCH_TRY(hipEventSynchronize(t1), "hipEventSynchronize");
+      float ms = 0.0f;
+      BATCH_TRY(hipEventElapsedTime(&ms, t0, t1), "hipEventElapsedTime");
+      if (!win || ms < best) {
+        best = ms;
+        win = v;
+      }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    R.v = win;
+  }
+  BATCH_TRY(upload_layout(R, batch_layout(soff, R.v->r, R.v->tj)), "layout");
+  BATCH_TRY(steps::launch_batch_init(d.counter, s), "init");
+  BATCH_TRY(batch_forces(R), "ensemble force");
+  c->batch_tile = steps_tile{R.v->r, R.v->tj, 1, R.v->variant};
+
+  // steps
+  const bool use_graph = (b->flags & STEPS_BATCH_GRAPH) != 0;
+  for (int k = 0; k < nsteps; ++k) {
+    if (b->resort_every > 0 && k > 0 && k % b->resort_every == 0) {
+      BATCH_TRY(batch_resort(R), "ensemble sort");
+    }
+    if (!use_graph) {
+      BATCH_TRY(batch_step(R), "ensemble step");
+      continue;
+    }
+    if (!exec) {
+      BATCH_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal),
+                "hipStreamBeginCapture");
+      hipError_t ce = batch_step(R);
+      hipError_t ee = hipStreamEndCapture(s, &graph);
+      BATCH_TRY(ce, "ensemble step capture");
+      BATCH_TRY(ee, "hipStreamEndCapture");
+      BATCH_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0),
+                "hipGraphInstantiate");
+    }
+    BATCH_TRY(hipGraphLaunch(exec, s), "hipGraphLaunch");
+  }
+
+  // back to the caller's order and arrays
+  BATCH_TRY(steps::launch_scatter_cols(d.pos, N, d.orig, N, b->pos, (int)Nc, 3, s), "scatter");
+  BATCH_TRY(steps::launch_scatter_cols(d.vel, N, d.orig, N, b->vel, (int)Nc, 3, s), "scatter");
+  BATCH_TRY(steps::launch_scatter_cols(d.acc, N, d.orig, N, b->acc, (int)Nc, 3, s), "scatter");
+  BATCH_TRY(hipStreamSynchronize(s), "ensemble run");
+#undef BATCH_TRY
+  batch_fail_cleanup(STEPS_OK, s, graph, exec);
+  write_status();
+  return STEPS_OK;
 }
 
 int steps_hubble(const steps_cosmology *cosmo, double a, double *out) {

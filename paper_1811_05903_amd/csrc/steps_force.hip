@@ -27,6 +27,8 @@
 //     loop with the Newtonian weight only -- no per-pair test at all.
 //     Otherwise it runs the tested loop.
 
+#include <algorithm>
+
 #include "steps_internal.h"
 
 namespace steps {
@@ -160,19 +162,22 @@ __device__ __forceinline__ bool tile_is_far(const double *__restrict__ ti,
 }
 
 // ---------------------------------------------------------------------------
-// FP64 kernel.  LDS tile: per j three double2 = (x, y), (z, m), (h, -).
+// One block's share of the sum, FP64.  The block owns the 256*R particles
+// [i0, min(i0 + 256 R, iend)) and sums over j in [jbeg, jend).  SoA arrays
+// have component stride `stride`; tinfo (CULL) points at the info of the
+// tile that starts at jbeg, tiles being consecutive from there.  Results go
+// to out[c * stride + i].  LDS tile: per j three double2 = (x, y), (z, m),
+// (h, -).  Must be called by all threads of the block.
 // ---------------------------------------------------------------------------
 template <int R, int TJ, bool E2, bool CULL>
-__global__ __launch_bounds__(kBlock) void k_force_f64(
+__device__ __forceinline__ void force_block_f64(
     const double *__restrict__ pos, const double *__restrict__ mass,
-    const double *__restrict__ soft, int n, int jchunk,
-    const double *__restrict__ tinfo, double *__restrict__ out) {
-  __shared__ double2 tile[3 * TJ];
+    const double *__restrict__ soft, int stride, int i0, int iend, int jbeg,
+    int jend, const double *__restrict__ tinfo, double *__restrict__ out,
+    double2 *tile) {
   const int tid = threadIdx.x;
-  const int ibase = blockIdx.x * (kBlock * R) + (tid >> 6) * (64 * R) + (tid & 63);
-  const int jbeg = blockIdx.y * jchunk;
-  const int jend = min(n, jbeg + jchunk);
-  const double *X = pos, *Y = pos + n, *Z = pos + 2 * (size_t)n;
+  const int ibase = i0 + (tid >> 6) * (64 * R) + (tid & 63);
+  const double *X = pos, *Y = pos + stride, *Z = pos + 2 * (size_t)stride;
 
   double xi[R], yi[R], zi[R], hi[R];
   double ax[R], ay[R], az[R], cx[R], cy[R], cz[R];  // total + compensation
@@ -180,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_force_f64(
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = ibase + 64 * r;
-    valid[r] = i < n;
+    valid[r] = i < iend;
     xi[r] = valid[r] ? X[i] : 0.0;
     yi[r] = valid[r] ? Y[i] : 0.0;
     zi[r] = valid[r] ? Z[i] : 0.0;
@@ -204,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_force_f64(
     __syncthreads();
 
     bool far = false;
-    if (CULL) far = tile_is_far(tinfo + (size_t)(jt / TJ) * 8, wb);
+    if (CULL) far = tile_is_far(tinfo + (size_t)((jt - jbeg) / TJ) * 8, wb);
 
     double tx[R], ty[R], tz[R];
 #pragma unroll
@@ -265,38 +270,34 @@ __global__ __launch_bounds__(kBlock) void k_force_f64(
     }
   }
 
-  double *o = out + (size_t)blockIdx.y * 3 * (size_t)n;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = ibase + 64 * r;
-    if (i < n) {
-      o[i] = ax[r] + cx[r];
-      o[(size_t)n + i] = ay[r] + cy[r];
-      o[2 * (size_t)n + i] = az[r] + cz[r];
+    if (i < iend) {
+      out[i] = ax[r] + cx[r];
+      out[(size_t)stride + i] = ay[r] + cy[r];
+      out[2 * (size_t)stride + i] = az[r] + cz[r];
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Mixed precision: pair arithmetic in FP32 on an FP32 shadow [5][n]
-// (x, y, z, m, h); v_rsq_f32 (~2^-23) used as is.  Each tile's FP32 partial
-// is added into an FP64 accumulator, or into a Kahan-compensated FP32
-// (sum, compensation) pair.  The inner loops use only two-operand VGPR
-// forms of the FP32 ops, which gfx950 issues from two waves per cycle.
-// LDS tile: float4 (x, y, z, m) and float h.
+// One block's share, mixed precision: pair arithmetic in FP32 on an FP32
+// shadow [5][stride] (x, y, z, m, h); v_rsq_f32 (~2^-23) used as is.  Each
+// tile's FP32 partial is added into an FP64 accumulator, or into a
+// Kahan-compensated FP32 (sum, compensation) pair.  The inner loops use
+// only two-operand VGPR forms of the FP32 ops, which gfx950 issues from two
+// waves per cycle.  LDS tile: float4 (x, y, z, m) and float h.
 // ---------------------------------------------------------------------------
 template <int R, int TJ, bool KAHAN, bool CULL>
-__global__ __launch_bounds__(kBlock) void k_force_mixed(
-    const float *__restrict__ shadow, int n, int jchunk,
-    const double *__restrict__ tinfo, double *__restrict__ out) {
-  __shared__ float4 tpos[TJ];
-  __shared__ float tsoft[TJ];
+__device__ __forceinline__ void force_block_mixed(
+    const float *__restrict__ shadow, int stride, int i0, int iend, int jbeg,
+    int jend, const double *__restrict__ tinfo, double *__restrict__ out,
+    float4 *tpos, float *tsoft) {
   const int tid = threadIdx.x;
-  const int ibase = blockIdx.x * (kBlock * R) + (tid >> 6) * (64 * R) + (tid & 63);
-  const int jbeg = blockIdx.y * jchunk;
-  const int jend = min(n, jbeg + jchunk);
-  const float *X = shadow, *Y = shadow + n, *Z = shadow + 2 * (size_t)n;
-  const float *M = shadow + 3 * (size_t)n, *H = shadow + 4 * (size_t)n;
+  const int ibase = i0 + (tid >> 6) * (64 * R) + (tid & 63);
+  const float *X = shadow, *Y = shadow + stride, *Z = shadow + 2 * (size_t)stride;
+  const float *M = shadow + 3 * (size_t)stride, *H = shadow + 4 * (size_t)stride;
 
   float xi[R], yi[R], zi[R], hi[R];
   bool valid[R];
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = ibase + 64 * r;
-    valid[r] = i < n;
+    valid[r] = i < iend;
     xi[r] = valid[r] ? X[i] : 0.0f;
     yi[r] = valid[r] ? Y[i] : 0.0f;
     zi[r] = valid[r] ? Z[i] : 0.0f;
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(
     __syncthreads();
 
     bool far = false;
-    if (CULL) far = tile_is_far(tinfo + (size_t)(jt / TJ) * 8, wb);
+    if (CULL) far = tile_is_far(tinfo + (size_t)((jt - jbeg) / TJ) * 8, wb);
 
     float tx[R], ty[R], tz[R];
 #pragma unroll
@@ -397,21 +398,98 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(
     }
   }
 
-  double *o = out + (size_t)blockIdx.y * 3 * (size_t)n;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = ibase + 64 * r;
-    if (i < n) {
+    if (i < iend) {
       if (KAHAN) {
-        o[i] = (double)sx[r] - (double)cx[r];
-        o[(size_t)n + i] = (double)sy[r] - (double)cy[r];
-        o[2 * (size_t)n + i] = (double)sz[r] - (double)cz[r];
+        out[i] = (double)sx[r] - (double)cx[r];
+        out[(size_t)stride + i] = (double)sy[r] - (double)cy[r];
+        out[2 * (size_t)stride + i] = (double)sz[r] - (double)cz[r];
       } else {
-        o[i] = ax[r];
-        o[(size_t)n + i] = ay[r];
-        o[2 * (size_t)n + i] = az[r];
+        out[i] = ax[r];
+        out[(size_t)stride + i] = ay[r];
+        out[2 * (size_t)stride + i] = az[r];
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Single-simulation kernels: block (x, y) = (i-block, j-split); split y
+// writes its partial to out + y * 3n.
+// ---------------------------------------------------------------------------
+template <int R, int TJ, bool E2, bool CULL>
+__global__ __launch_bounds__(kBlock) void k_force_f64(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ soft, int n, int jchunk,
+    const double *__restrict__ tinfo, double *__restrict__ out) {
+  __shared__ double2 tile[3 * TJ];
+  const int jbeg = blockIdx.y * jchunk;
+  force_block_f64<R, TJ, E2, CULL>(
+      pos, mass, soft, n, blockIdx.x * (kBlock * R), n, jbeg,
+      min(n, jbeg + jchunk), CULL ? tinfo + (size_t)(jbeg / TJ) * 8 : nullptr,
+      out + (size_t)blockIdx.y * 3 * (size_t)n, tile);
+}
+
+template <int R, int TJ, bool KAHAN, bool CULL>
+__global__ __launch_bounds__(kBlock) void k_force_mixed(
+    const float *__restrict__ shadow, int n, int jchunk,
+    const double *__restrict__ tinfo, double *__restrict__ out) {
+  __shared__ float4 tpos[TJ];
+  __shared__ float tsoft[TJ];
+  const int jbeg = blockIdx.y * jchunk;
+  force_block_mixed<R, TJ, KAHAN, CULL>(
+      shadow, n, blockIdx.x * (kBlock * R), n, jbeg, min(n, jbeg + jchunk),
+      CULL ? tinfo + (size_t)(jbeg / TJ) * 8 : nullptr,
+      out + (size_t)blockIdx.y * 3 * (size_t)n, tpos, tsoft);
+}
+
+// ---------------------------------------------------------------------------
+// Ensemble kernels: a persistent grid pulls work items from an atomic
+// counter until none are left (every block then returns, so the grid always
+// drains).  Item k is the block of particles [it.x, it.y) of one member
+// against that member's whole range [it.z, it.w); tbase[k] is the index of
+// the member's first tile in tinfo.  Items are ordered longest first.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int next_item(int *counter, int *slot) {
+  __syncthreads();  // everyone has read the previous item
+  if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+  __syncthreads();
+  return *slot;
+}
+
+template <int R, int TJ, bool E2>
+__global__ __launch_bounds__(kBlock) void k_batch_force_f64(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ soft, int stride, const int4 *__restrict__ items,
+    const int *__restrict__ tbase, int nitems,
+    const double *__restrict__ tinfo, double *__restrict__ out, int *counter) {
+  __shared__ double2 tile[3 * TJ];
+  __shared__ int slot;
+  for (int it = next_item(counter, &slot); it < nitems;
+       it = next_item(counter, &slot)) {
+    const int4 w = items[it];
+    force_block_f64<R, TJ, E2, true>(pos, mass, soft, stride, w.x, w.y, w.z,
+                                     w.w, tinfo + (size_t)tbase[it] * 8, out,
+                                     tile);
+  }
+}
+
+template <int R, int TJ, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_batch_force_mixed(
+    const float *__restrict__ shadow, int stride, const int4 *__restrict__ items,
+    const int *__restrict__ tbase, int nitems,
+    const double *__restrict__ tinfo, double *__restrict__ out, int *counter) {
+  __shared__ float4 tpos[TJ];
+  __shared__ float tsoft[TJ];
+  __shared__ int slot;
+  for (int it = next_item(counter, &slot); it < nitems;
+       it = next_item(counter, &slot)) {
+    const int4 w = items[it];
+    force_block_mixed<R, TJ, KAHAN, true>(shadow, stride, w.x, w.y, w.z, w.w,
+                                          tinfo + (size_t)tbase[it] * 8, out,
+                                          tpos, tsoft);
   }
 }
 
@@ -442,6 +520,46 @@ hipError_t launch_mixed(const ForceLaunch &L, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Persistent ensemble launch: grid = CUs x resident blocks per CU.
+template <typename K>
+int persistent_grid(K kernel) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, 0) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return 2048;
+  }
+  return std::max(1, cus * std::max(1, per));
+}
+
+template <int R, int TJ, bool E2>
+hipError_t launch_batch_f64(const BatchLaunch &L, hipStream_t s) {
+  static const int grid = persistent_grid(k_batch_force_f64<R, TJ, E2>);
+  hipLaunchKernelGGL((k_batch_force_f64<R, TJ, E2>), dim3(grid), dim3(kBlock),
+                     0, s, L.pos, L.mass, L.soft, L.stride, L.items, L.tbase,
+                     L.nitems, L.tinfo, L.out, L.counter);
+  return hipGetLastError();
+}
+
+template <int R, int TJ>
+hipError_t launch_batch_mixed(const BatchLaunch &L, hipStream_t s) {
+  if (L.kahan) {
+    static const int grid = persistent_grid(k_batch_force_mixed<R, TJ, true>);
+    hipLaunchKernelGGL((k_batch_force_mixed<R, TJ, true>), dim3(grid),
+                       dim3(kBlock), 0, s, L.shadow, L.stride, L.items,
+                       L.tbase, L.nitems, L.tinfo, L.out, L.counter);
+  } else {
+    static const int grid = persistent_grid(k_batch_force_mixed<R, TJ, false>);
+    hipLaunchKernelGGL((k_batch_force_mixed<R, TJ, false>), dim3(grid),
+                       dim3(kBlock), 0, s, L.shadow, L.stride, L.items,
+                       L.tbase, L.nitems, L.tinfo, L.out, L.counter);
+  }
+  return hipGetLastError();
+}
+
 // variant bits: 1 = FP64 weight without the e^2 term; 2 = sorted input with
 // (wave, tile) culling of the softening test.
 #define F64_SET(R)                                                  \
@@ -458,6 +576,17 @@ const ForceVariant kVariants[] = {
     MIXED_SET(1, 128),  MIXED_SET(2, 256),  MIXED_SET(4, 256),  MIXED_SET(8, 256),
 };
 
+// ensemble variants: always culled (the ensemble keeps its state sorted)
+const BatchVariant kBatchVariants[] = {
+    {kClassF64, 2, 128, 2, launch_batch_f64<2, 128, true>},
+    {kClassF64, 2, 128, 3, launch_batch_f64<2, 128, false>},
+    {kClassF64, 4, 128, 2, launch_batch_f64<4, 128, true>},
+    {kClassF64, 4, 128, 3, launch_batch_f64<4, 128, false>},
+    {kClassMixed, 1, 128, 2, launch_batch_mixed<1, 128>},
+    {kClassMixed, 2, 256, 2, launch_batch_mixed<2, 256>},
+    {kClassMixed, 4, 256, 2, launch_batch_mixed<4, 256>},
+};
+
 }  // namespace
 
 const ForceVariant *force_variants(int *count) {
@@ -472,6 +601,11 @@ const ForceVariant *find_force_variant(int cls, int r, int tj, int variant) {
     }
   }
   return nullptr;
+}
+
+const BatchVariant *batch_variants(int *count) {
+  *count = (int)(sizeof(kBatchVariants) / sizeof(kBatchVariants[0]));
+  return kBatchVariants;
 }
 
 }  // namespace steps

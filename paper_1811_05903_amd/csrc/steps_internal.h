@@ -39,6 +39,58 @@ struct ForceVariant {
   hipError_t (*launch)(const ForceLaunch &, hipStream_t);
 };
 
+// Arguments of one persistent ensemble force launch (sorted state, culled).
+struct BatchLaunch {
+  const double *pos = nullptr, *mass = nullptr, *soft = nullptr;  // FP64 [.][stride]
+  const float *shadow = nullptr;  // mixed: [5][stride]
+  int stride = 0;                 // total particles of the ensemble
+  const int4 *items = nullptr;    // (i0, iend, jbeg, jend) per work item
+  const int *tbase = nullptr;     // first tile of the item's member
+  int nitems = 0;
+  const double *tinfo = nullptr;  // [tiles][8]
+  double *out = nullptr;          // [3][stride]
+  int *counter = nullptr;         // work counter, 0 before the launch
+  int kahan = 0;
+};
+
+struct BatchVariant {
+  int cls, r, tj, variant;
+  hipError_t (*launch)(const BatchLaunch &, hipStream_t);
+};
+const BatchVariant *batch_variants(int *count);
+
+// ---- ensemble O(N) kernels (steps_batch.hip) ----------------------------
+// per (step, member) scalars: hdt, G/a0^3, radial/a0^3, 2H(a0), dt,
+// G/a1^3, radial/a1^3, 1/(1 + 2H(a1) hdt)
+constexpr int kBatchScalars = 8;
+hipError_t launch_batch_init(int *counter, hipStream_t s);
+hipError_t launch_batch_kick_drift(double *pos, double *vel, const double *S,
+                                   float *shadow, const int *mid, int n,
+                                   const double *table, int members,
+                                   int nsteps, int *counter, hipStream_t s);
+hipError_t launch_batch_kick_end(const double *pos, double *vel,
+                                 const double *S, const int *mid, int n,
+                                 const double *table, int members, int nsteps,
+                                 const int *counter, hipStream_t s);
+hipError_t launch_batch_advance(int *counter, hipStream_t s);
+hipError_t launch_batch_tile_info_f64(const double *soa, int stride,
+                                      const int *beg, const int *end,
+                                      int ntiles, double *info, hipStream_t s);
+hipError_t launch_batch_tile_info_f32(const float *soa, int stride,
+                                      const int *beg, const int *end,
+                                      int ntiles, double *info, hipStream_t s);
+hipError_t launch_batch_morton(const double *pos, int n, const double *box,
+                               const int *mid, int qbits,
+                               unsigned long long *keys, int *vals,
+                               hipStream_t s);
+hipError_t launch_gather_cols(const double *src, int ss, const int *idx, int n,
+                              double *dst, int ds, int comps, hipStream_t s);
+hipError_t launch_gather_int(const int *src, const int *idx, int n, int *dst,
+                             hipStream_t s);
+hipError_t launch_scatter_cols(const double *src, int ss, const int *idx,
+                               int n, double *dst, int ds, int comps,
+                               hipStream_t s);
+
 // All compiled force-kernel variants.
 const ForceVariant *force_variants(int *count);
 const ForceVariant *find_force_variant(int cls, int r, int tj, int variant);

@@ -1,0 +1,219 @@
+"""GPU tests of the ensemble path (steps_batch_run): every member against the
+oracle run on its own, graph replay against one-by-one launches (bitwise),
+skipped members, mixed precision and the autotuner."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def st():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1811_05903_amd as m
+    m.load()
+    return m
+
+
+NSTEPS = 12
+
+
+def _members():
+    # uneven sizes (one empty, one single particle, one ragged), two
+    # cosmologies, different step ranges
+    specs = [(700, 0.30, 0.02, 0.05), (1, 0.30, 0.02, 0.04), (0, 0.25, 0.02, 0.05),
+             (1537, 0.35, 0.03, 0.06), (2048, 0.28, 0.02, 0.05)]
+    out = []
+    for b, (n, om, a0, a1) in enumerate(specs):
+        c = synth.Cosmo(H0=70.0, omega_m=om, omega_l=1.0 - om)
+        ps = synth.make_set(max(n, 1), 100.0, 1000.0, c, 0.01, 9000 + b, a0, a1,
+                            NSTEPS, zeldovich=True)
+        if n == 0:
+            ps.pos, ps.vel = ps.pos[:, :0], ps.vel[:, :0]
+            ps.mass, ps.soft = ps.mass[:0], ps.soft[:0]
+        out.append(ps)
+    return out
+
+
+def _arena(members):
+    offs = np.cumsum([0] + [m.n for m in members])
+    cat = lambda key, axis: np.ascontiguousarray(
+        np.concatenate([getattr(m, key) for m in members], axis=axis))
+    return offs, cat("pos", 1), cat("vel", 1), cat("mass", 0), cat("soft", 0)
+
+
+def _grid(a0, a1, n):
+    # the library's grid: a_k = a0 (a1/a0)^(k/n), end points exact
+    g = a0 * np.exp(np.log(a1 / a0) * np.arange(n + 1) / n)
+    g[0], g[-1] = a0, a1
+    return g
+
+
+def _run(st, members, flags, ctx=None, resort=0, cosmos=None):
+    import torch
+    offs, pos, vel, mass, soft = _arena(members)
+    p, v = dev(pos), dev(vel)
+    acc = torch.zeros_like(p)
+    cs = cosmos or [st.Cosmology(m.cosmo.H0, m.cosmo.omega_m, m.cosmo.omega_l)
+                    for m in members]
+    status = st.steps_batch_run(p, v, dev(mass), dev(soft), acc, offs, cs,
+                                [m.a0 for m in members], [m.a1 for m in members],
+                                NSTEPS, flags=flags, resort_every=resort, ctx=ctx)
+    return status, host(p), host(v), host(acc), offs
+
+
+def test_batch_matches_oracle_per_member(st):
+    members = _members()
+    status, p, v, acc, offs = _run(st, members, st.STEPS_BATCH_GRAPH)
+    assert status == [0] * len(members)
+    for b, m in enumerate(members):
+        if m.n == 0:
+            continue
+        oc = oracle.Cosmology(m.cosmo.H0, m.cosmo.omega_m, m.cosmo.omega_l)
+        po, vo, So = oracle.run(m.pos, m.vel, m.mass, m.soft,
+                                _grid(m.a0, m.a1, NSTEPS), oc)
+        sl = slice(offs[b], offs[b + 1])
+        dx = np.linalg.norm(p[:, sl] - po, axis=0) / m.soft
+        vs = max(np.linalg.norm(vo, axis=0).max(), 1e-30)
+        dv = np.linalg.norm(v[:, sl] - vo, axis=0) / vs
+        print("member %d n=%d |dx|/h median %.2e max %.2e |dv| %.2e"
+              % (b, m.n, np.median(dx), dx.max(), dv.max()))
+        # Trajectory bar: force parity is 1e-12, but over 12 long steps a
+        # particle in a close encounter amplifies rounding-level force
+        # differences (every GPU launch shape, sorted or not, shows the same
+        # ~5e-9 on one particle of member 4, while the oracle is
+        # order-independent to the bit).  The median stays at rounding level.
+        assert np.median(dx) < 1e-10 and dx.max() < 1e-7
+        assert dv.max() < 1e-9
+        if m.n > 1:
+            dS = np.linalg.norm(acc[:, sl] - So, axis=0) / np.linalg.norm(So, axis=0)
+            assert np.median(dS) < 1e-10
+
+
+def test_graph_replay_bitwise_equals_launches(st):
+    members = _members()
+    a = _run(st, members, st.STEPS_BATCH_GRAPH)
+    b = _run(st, members, 0)
+    c = _run(st, members, st.STEPS_BATCH_GRAPH)
+    for x, y, z in zip(a[1:4], b[1:4], c[1:4]):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+def test_bad_member_skipped_others_run(st):
+    members = _members()
+    cs = [st.Cosmology(m.cosmo.H0, m.cosmo.omega_m, m.cosmo.omega_l)
+          for m in members]
+    cs[3] = st.Cosmology(-70.0, 0.3, 0.7)           # invalid H0
+    status, p, v, acc, offs = _run(st, members, st.STEPS_BATCH_GRAPH, cosmos=cs)
+    assert status[3] == st.STEPS_E_INVAL
+    assert [s for i, s in enumerate(status) if i != 3] == [0] * (len(members) - 1)
+    sl = slice(offs[3], offs[4])
+    _, pos0, vel0, _, _ = _arena(members)
+    assert np.array_equal(p[:, sl], pos0[:, sl])      # untouched
+    assert np.all(acc[:, sl] == 0.0)
+    # the other members run as without member 3 (up to summation order: the
+    # spatial order is taken over the active members' common bounding box)
+    ref = _run(st, members, st.STEPS_BATCH_GRAPH)
+    for b in (0, 1, 4):
+        sl0 = slice(offs[b], offs[b + 1])
+        dx = np.linalg.norm(p[:, sl0] - ref[1][:, sl0], axis=0) / members[b].soft
+        assert np.median(dx) < 1e-10 and dx.max() < 1e-7
+
+
+def _zero_step_forces(st, members, ctx, flags=0):
+    # a1 = a0: every step has dt = 0, so the run leaves pos, vel as they are
+    # and returns acc = S(pos) from the ensemble force kernel
+    import torch
+    offs, pos, vel, mass, soft = _arena(members)
+    p, v = dev(pos), dev(vel)
+    acc = torch.zeros_like(p)
+    cs = [st.Cosmology(m.cosmo.H0, m.cosmo.omega_m, m.cosmo.omega_l)
+          for m in members]
+    a0 = [m.a0 for m in members]
+    status = st.steps_batch_run(p, v, dev(mass), dev(soft), acc, offs, cs, a0,
+                                a0, 1, flags=flags, ctx=ctx)
+    assert status == [0] * len(members)
+    assert np.array_equal(host(p), pos) and np.array_equal(host(v), vel)
+    return host(acc), offs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "kahan"])
+def test_batch_forces_match_oracle(st, prec):
+    members = _members()
+    ctx = st.Context(0, precision=prec)
+    acc, offs = _zero_step_forces(st, members, ctx, st.STEPS_BATCH_AUTOTUNE)
+    tile = st.steps_batch_tile(ctx)
+    ctx.close()
+    assert tile["r"] in ((2, 4) if prec == "fp64" else (1, 2, 4))
+    for b, m in enumerate(members):
+        if m.n < 2:
+            continue
+        ref = oracle.forces(m.pos, m.mass, m.soft)
+        err = np.linalg.norm(acc[:, offs[b]:offs[b + 1]] - ref, axis=0) / \
+            np.linalg.norm(ref, axis=0)
+        print("%s member %d n=%d force err median %.2e max %.2e"
+              % (prec, b, m.n, np.median(err), err.max()))
+        if prec == "fp64":
+            assert err.max() <= 1e-12
+        else:
+            assert np.median(err) <= 1e-5 and err.max() <= 1e-4
+
+
+def test_batch_mixed_trajectory_close_to_fp64(st):
+    # Gross-error guard only: over 12 long steps the dynamics amplify force
+    # differences ~5e3-fold in |dx|/h (measured with FP64 against the oracle:
+    # 1e-15 forces -> 5e-12 positions), so FP32 pair errors (~5e-7) show up
+    # as ~1e-3 h; a wrong member mapping or tile would give O(1).
+    members = _members()
+    ctx = st.Context(0, precision="mixed")
+    status, pm, _, _, offs = _run(st, members, st.STEPS_BATCH_GRAPH, ctx=ctx)
+    ctx.close()
+    assert status == [0] * len(members)
+    _, pf, _, _, _ = _run(st, members, st.STEPS_BATCH_GRAPH)
+    for b, m in enumerate(members):
+        if m.n:
+            sl = slice(offs[b], offs[b + 1])
+            dx = np.linalg.norm(pm[:, sl] - pf[:, sl], axis=0) / m.soft
+            print("mixed vs fp64 member %d: |dx|/h median %.2e max %.2e"
+                  % (b, np.median(dx), dx.max()))
+            assert np.median(dx) < 1e-2, (b, np.median(dx))
+
+
+def test_resort_between_steps(st):
+    members = _members()
+    a = _run(st, members, st.STEPS_BATCH_GRAPH, resort=0)
+    b = _run(st, members, st.STEPS_BATCH_GRAPH, resort=3)
+    _, _, _, _, offs = a
+    for k, m in enumerate(members):
+        if m.n:
+            sl = slice(offs[k], offs[k + 1])
+            dx = np.linalg.norm(a[1][:, sl] - b[1][:, sl], axis=0) / m.soft
+            assert np.median(dx) < 1e-10 and dx.max() < 1e-7
+
+
+def test_batch_argument_errors(st):
+    import torch
+    members = _members()
+    offs, pos, vel, mass, soft = _arena(members)
+    p, v, m_, h = dev(pos), dev(vel), dev(mass), dev(soft)
+    acc = torch.zeros_like(p)
+    cs = [st.Cosmology() for _ in members]
+    a0 = [0.02] * len(members)
+    with pytest.raises(st.StepsError):   # offsets decrease
+        bad = list(offs)
+        bad[1], bad[2] = bad[2], bad[1]   # 700 and 701 swapped
+        st.steps_batch_run(p, v, m_, h, acc, bad, cs, a0, a0, 5)
+    with pytest.raises(st.StepsError):   # nsteps < 1
+        st.steps_batch_run(p, v, m_, h, acc, offs, cs, a0, a0, 0)
+    with pytest.raises(st.StepsError):   # pos and vel overlap
+        st.steps_batch_run(p, p, m_, h, acc, offs, cs, a0, a0, 5)
+    with pytest.raises(st.StepsError):   # unknown flag
+        st.steps_batch_run(p, v, m_, h, acc, offs, cs, a0, a0, 5, flags=64)
+    assert np.array_equal(host(p), pos)
