@@ -70,6 +70,9 @@ def _load():
         lib.oracle_kdk_step.argtypes = [i64, vp, vp, vp, vp, vp, d, d,
                                         ctypes.POINTER(_Cosmo), i32]
         lib.oracle_kdk_step.restype = i32
+        lib.oracle_energy.argtypes = [i64, vp, vp, vp, vp, d,
+                                      ctypes.POINTER(_Cosmo), vp, i32]
+        lib.oracle_energy.restype = i32
         lib.oracle_G.argtypes = []
         lib.oracle_G.restype = d
         lib.oracle_kms_to_mpc_per_gyr.argtypes = []
@@ -219,6 +222,40 @@ def kdk_step(pos, vel, mass, soft, S, a, da, cosmo: Cosmology, nthreads=0):
                                  ctypes.byref(c), int(nthreads))
     if rc:
         raise ValueError("oracle_kdk_step: bad argument")
+
+
+def energy(pos, vel, mass, soft, a, cosmo: Cosmology, nthreads=0):
+    """Comoving energies (derived from Eq. 8; see oracle.c): dict with K, W,
+    U_pair, U_radial and P (peculiar momentum sum m a^2 v)."""
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    n = mass.shape[0]
+    pos, vel = _soa(pos, n), _soa(vel, n)
+    soft = np.ascontiguousarray(soft, dtype=np.float64)
+    out = np.zeros(7)
+    c = cosmo._c()
+    rc = _load().oracle_energy(n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(soft),
+                               float(a), ctypes.byref(c), _ptr(out),
+                               int(nthreads))
+    if rc:
+        raise ValueError("oracle_energy: bad argument")
+    return {"K": out[0], "W": out[1], "U_pair": out[2], "U_radial": out[3],
+            "P": out[4:7].copy()}
+
+
+def layzer_irvine(energies, a_grid, cosmo: Cosmology):
+    """Residual R_n = (K+W)_n - (K+W)_0 + int_0^t H (2K + W) dt' of the
+    cosmic energy equation, the integral by the trapezoid rule over the
+    steps of a_grid (energies[k] at a_grid[k])."""
+    out = [0.0]
+    acc = 0.0
+    e0 = energies[0]["K"] + energies[0]["W"]
+    for k in range(1, len(energies)):
+        t = dt(a_grid[k - 1], a_grid[k] - a_grid[k - 1], cosmo)
+        f0 = hubble(a_grid[k - 1], cosmo) * (2 * energies[k - 1]["K"] + energies[k - 1]["W"])
+        f1 = hubble(a_grid[k], cosmo) * (2 * energies[k]["K"] + energies[k]["W"])
+        acc += 0.5 * (f0 + f1) * t
+        out.append(energies[k]["K"] + energies[k]["W"] - e0 + acc)
+    return np.array(out)
 
 
 def run(pos, vel, mass, soft, a_grid, cosmo: Cosmology, nthreads=0):

@@ -340,6 +340,63 @@ int oracle_kdk_step(int64_t n, double *pos, double *vel, const double *mass,
   return 0;
 }
 
+/* ---- comoving energies, for the Layzer-Irvine check -------------------- */
+
+/*
+ * The paper states no energy diagnostic; this one follows from Eq. 8.  With
+ * the canonical momentum p = m a^2 dx/dt, Eq. 8 reads dp/dt = -grad U_c / a
+ * for the comoving potential energy
+ *   U_c = (G/2) sum_{i != j} m_i m_j phi(r_ij, h_i + h_j)
+ *         - (Omega_m H0^2 / 4) sum_i m_i |x_i|^2,
+ * whose gradient is the pair force plus the radial term (Omega_m H0^2 / 2) x.
+ * With K = (1/2) sum m a^2 |v|^2 and W = U_c / a this gives the cosmic energy
+ * equation d(K + W)/dt = -H (2K + W).  In the Newtonian test mode a = 1 and
+ * the radial term is absent.
+ *
+ * out[0] = K, out[1] = W, out[2] = pair part of U_c, out[3] = radial part,
+ * out[4..6] = sum m a^2 v (peculiar momentum; not conserved: the radial term
+ * pushes outwards).  Returns 0, or -1 on a bad argument.
+ */
+int oracle_energy(int64_t n, const double *pos, const double *vel,
+                  const double *mass, const double *soft, double a,
+                  const oracle_cosmo *c, double *out, int nthreads) {
+  if (n < 0 || !c || !out || (n > 0 && (!pos || !vel || !mass || !soft))) {
+    return -1;
+  }
+  if (c->newtonian_test) a = 1.0;
+  if (!(a > 0.0)) return -1;
+  double *phi = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+  if (!phi) return -1;
+  int rc = oracle_potential(n, pos, mass, soft, n, NULL, phi, nthreads);
+  if (rc) {
+    free(phi);
+    return rc;
+  }
+  double h0 = c->H0 * oracle_kms_to_mpc_per_gyr();
+  double rad = c->newtonian_test ? 0.0 : 0.25 * c->omega_m * h0 * h0;
+  nsum kin = {0, 0}, upair = {0, 0}, urad = {0, 0};
+  nsum px = {0, 0}, py = {0, 0}, pz = {0, 0};
+  for (int64_t i = 0; i < n; ++i) {
+    double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
+    double x = pos[i], y = pos[n + i], z = pos[2 * n + i];
+    nsum_add(&kin, 0.5 * mass[i] * a * a * (vx * vx + vy * vy + vz * vz));
+    nsum_add(&upair, 0.5 * c->G * mass[i] * phi[i]);
+    nsum_add(&urad, -rad * mass[i] * (x * x + y * y + z * z));
+    nsum_add(&px, mass[i] * a * a * vx);
+    nsum_add(&py, mass[i] * a * a * vy);
+    nsum_add(&pz, mass[i] * a * a * vz);
+  }
+  free(phi);
+  out[0] = nsum_get(&kin);
+  out[2] = nsum_get(&upair);
+  out[3] = nsum_get(&urad);
+  out[1] = (out[2] + out[3]) / a;
+  out[4] = nsum_get(&px);
+  out[5] = nsum_get(&py);
+  out[6] = nsum_get(&pz);
+  return 0;
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();
