@@ -82,6 +82,10 @@ def main():
     torch.cuda.set_device(0)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
+    if args.workload == 5:
+        print(json.dumps(workload5(st, dev, args)), flush=True)
+        return
+
     ps = synth.config(args.workload)
     n = ps.n
     log("workload %d: n=%d precision=%s" % (args.workload, n, args.precision))
@@ -166,9 +170,9 @@ def main():
         log("cpu baseline: oracle on %d sampled rows (%d threads)" % (m, oracle.num_threads()))
         # the same positions the GPU starts from (before stepping)
         t = time.perf_counter()
-        ref = oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx)
+        ref, kap = oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx, want_kappa=True)
         dt = time.perf_counter() - t
-        sample_rows = (idx, ref)
+        sample_rows = (idx, ref, kap)
         out["cpu_baseline"] = {
             "value": m * float(n) / dt, "unit": "pairs/s",
             "cores": oracle.num_threads(), "kind": "oracle",
@@ -182,7 +186,8 @@ def main():
         if not args.no_cpu_baseline:
             import oracle
             bidx = np.sort(np.random.default_rng(3).choice(big.n, 32, replace=False))
-            big_rows = (bidx, oracle.forces(big.pos, big.mass, big.soft, idx=bidx))
+            big_rows = (bidx,) + oracle.forces(big.pos, big.mass, big.soft, idx=bidx,
+                                               want_kappa=True)
         out["modes_n2e21"] = mode_table(st, big, big_rows, dev)
     if not args.no_batch:
         out["batch"] = batch_leg(st, dev, args.batch_steps)
@@ -219,6 +224,102 @@ def profiled_traffic(precision, tile, workload):
             ok = (os.path.exists(src) and
                   hashlib.sha256(open(src, "rb").read()).hexdigest() == digest)
     return traffic if ok else None
+
+
+def workload5(st, dev, args):
+    """Workload 5: N = 2^22 (D = 500, r_max = 4000, LCDM 0.3089/0.6911/
+    67.74, sigma 1%, Zel'dovich velocities), 50 log steps a 0.1 -> 1.0.
+    The mixed-precision run is checked against the FP64 GPU run: force
+    error at the start (all particles, plus an oracle spot check on sampled
+    rows), Layzer-Irvine energy residual every 25 steps, final positions.
+    --steps sets the step count here (default 50, the full run)."""
+    import numpy as np
+    import torch
+    import synth
+    ps = synth.config(5)
+    n, grid, c = ps.n, ps.a_grid(), ps.cosmo
+    nsteps = min(args.steps if args.steps != 20 else 50, len(grid) - 1)
+    cosmo = st.Cosmology(c.H0, c.omega_m, c.omega_l, c.omega_r)
+    m, h = dev(ps.mass), dev(ps.soft)
+    every = 25   # energy (an O(N^2) FP64 potential) every this many steps
+    log("workload 5: n=%d, %d steps a %.2f -> %.2f" % (n, nsteps, grid[0], grid[nsteps]))
+    res = {}
+    acc0 = {}
+    for prec in ("mixed", "fp64"):
+        ctx = st.Context(0, precision=prec, flags=st.STEPS_PROFILE)
+        p, v = dev(ps.pos), dev(ps.vel)
+        acc = st.steps_forces(p, m, h, ctx=ctx)
+        acc0[prec] = acc.cpu().numpy()
+        es = [st.steps_energy(p, v, m, h, grid[0], cosmo, ctx=ctx)]
+        ctx.force_timing(reset=True)
+        t_steps = 0.0
+        for k in range(nsteps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], cosmo, ctx=ctx)
+            torch.cuda.synchronize()
+            t_steps += time.perf_counter() - t0
+            if (k + 1) % every == 0 or k + 1 == nsteps:
+                es.append(st.steps_energy(p, v, m, h, grid[k + 1], cosmo, ctx=ctx))
+            log("%s step %d/%d a=%.4f (%.2f s/step)" % (prec, k + 1, nsteps, grid[k + 1], t_steps / (k + 1)))
+        kms, cnt = ctx.force_timing(reset=True)
+        ks = [0] + [k for k in range(every, nsteps + 1, every)] + ([nsteps] if nsteps % every else [])
+        ga = [grid[k] for k in ks]
+        # trapezoid over the energy sample points
+        R, acc_int, e0 = [0.0], 0.0, es[0]["K"] + es[0]["W"]
+        for q in range(1, len(es)):
+            tt = st.steps_dt(cosmo, ga[q - 1], ga[q] - ga[q - 1])
+            f0 = st.steps_hubble(cosmo, ga[q - 1]) * (2 * es[q - 1]["K"] + es[q - 1]["W"])
+            f1 = st.steps_hubble(cosmo, ga[q]) * (2 * es[q]["K"] + es[q]["W"])
+            acc_int += 0.5 * (f0 + f1) * tt
+            R.append(es[q]["K"] + es[q]["W"] - e0 + acc_int)
+        wscale = max(abs(e["W"]) for e in es)
+        pairs = float(n) * n
+        res[prec] = {"steps": nsteps, "step_s": t_steps / nsteps,
+                     "pairs_per_s": pairs * nsteps / t_steps,
+                     "force_kernel_ms": kms / cnt,
+                     "force_pairs_per_s": pairs / (kms / cnt * 1e-3),
+                     "tflops_20": FLOP_PER_PAIR * pairs / (kms / cnt * 1e-3) / 1e12,
+                     "frac_peak": FLOP_PER_PAIR * pairs / (kms / cnt * 1e-3) / 1e12
+                     / (FP64_PEAK_TF if prec == "fp64" else FP32_PEAK_TF),
+                     "layzer_irvine_a": ga, "layzer_irvine_rel": [r / wscale for r in R],
+                     "energies": [{"K": e["K"], "W": e["W"]} for e in es],
+                     "tile": ctx.get_tile(n)}
+        res[prec + "_final_pos"] = p.cpu().numpy()
+        ctx.close()
+    dpos = np.linalg.norm(res.pop("mixed_final_pos") - res.pop("fp64_final_pos"), axis=0) / ps.soft
+    ferr = np.linalg.norm(acc0["mixed"] - acc0["fp64"], axis=0) / np.linalg.norm(acc0["fp64"], axis=0)
+    out = {"metric": "pair interactions/s (ordered pairs, whole KDK step)",
+           "value": res["mixed"]["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1,
+           "steps": nsteps, "warmup": 0, "ms_per_step": 1e3 * res["mixed"]["step_s"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32-pair/f64-acc", "data": "synthetic",
+           "config": {"workload": "stereographic sphere N=%d D=500 r_max=4000 LCDM, "
+                                  "mixed forces, FP64 kick/drift, a 0.1 -> 1.0" % n,
+                      "n": n, "parallelism": "single GPU"},
+           "mixed": res["mixed"], "fp64": res["fp64"],
+           "mixed_vs_fp64_force_rel_err_start": {"median": float(np.median(ferr)),
+                                                  "max": float(ferr.max())},
+           "mixed_vs_fp64_final_dx_over_h": {"median": float(np.median(dpos)),
+                                              "p99": float(np.quantile(dpos, 0.99))}}
+    if not args.no_cpu_baseline:
+        import oracle
+        idx = np.sort(np.random.default_rng(5).choice(n, 4096, replace=False))
+        t0 = time.perf_counter()
+        ref = oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx)
+        tcpu = time.perf_counter() - t0
+        for prec in ("mixed", "fp64"):
+            e = np.linalg.norm(acc0[prec][:, idx] - ref, axis=0) / np.linalg.norm(ref, axis=0)
+            out[prec]["oracle_rel_err"] = {"rows": 4096, "median": float(np.median(e)),
+                                           "max": float(e.max())}
+        out["cpu_baseline"] = {"value": 4096.0 * n / tcpu, "unit": "pairs/s",
+                               "cores": oracle.num_threads(), "kind": "oracle",
+                               "sample": "FP64 oracle pair sums for 4096 seeded-sampled "
+                                         "i against all %d j (%.1f s)" % (n, tcpu)}
+    log("workload 5: mixed %.3e pairs/s, fp64 %.3e; LI drift mixed %.2e fp64 %.2e"
+        % (res["mixed"]["pairs_per_s"], res["fp64"]["pairs_per_s"],
+           abs(res["mixed"]["layzer_irvine_rel"][-1]), abs(res["fp64"]["layzer_irvine_rel"][-1])))
+    return out
 
 
 def batch_leg(st, dev, nsteps):
@@ -280,6 +381,25 @@ def batch_leg(st, dev, nsteps):
                     "and initial force evaluation"}
 
 
+def binned_errors(err, kappa, radius, nbins=3):
+    """Median and max relative error in equal-count bins of the oracle's
+    condition number kappa (sum of |pair terms| over |S|) and of the
+    distance from the centre."""
+    import numpy as np
+    out = {}
+    for name, key in (("kappa", kappa), ("radius", radius)):
+        order = np.argsort(key)
+        bins = []
+        for part in np.array_split(order, min(nbins, max(1, order.size))):
+            if part.size == 0:
+                continue
+            bins.append({"lo": float(key[part[0]]), "hi": float(key[part[-1]]),
+                         "median": float(np.median(err[part])),
+                         "max": float(err[part].max()), "rows": int(part.size)})
+        out[name] = bins
+    return out
+
+
 def mode_table(st, ps, rows, dev):
     """Force-kernel rate per precision mode at this N, one timed launch after
     one warm-up, and the error against the oracle rows if given."""
@@ -305,12 +425,13 @@ def mode_table(st, ps, rows, dev):
                  "frac_peak": FLOP_PER_PAIR * rate / 1e12 / peak,
                  "tile": ctx.get_tile(n)}
         if rows is not None:
-            idx, ref = rows
+            idx, ref, kap = rows
             got = acc.cpu().numpy()[:, idx]
             err = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
             entry["rel_err_median"] = float(np.median(err))
             entry["rel_err_max"] = float(err.max())
             entry["rel_err_rows"] = int(idx.size)
+            entry["rel_err_binned"] = binned_errors(err, kap, np.linalg.norm(ps.pos[:, idx], axis=0))
         res[prec] = entry
         log("n=%d %s: %.2f ms, %.3e pairs/s%s" % (
             n, prec, kms, rate,

@@ -131,6 +131,11 @@ int steps_ctx_set_flags(steps_ctx *ctx, uint32_t flags);
  * must name one of them, jsplit >= 1).  Passing NULL returns to automatic
  * selection (tuned table, else heuristic). */
 int steps_ctx_set_tile(steps_ctx *ctx, const steps_tile *tile);
+/* Record `tile` as the tuned shape for n particles in the context's current
+ * precision, as steps_autotune would (validated like steps_ctx_set_tile;
+ * replaces an earlier entry for the same precision and n).  For restoring a
+ * shape found by an earlier steps_autotune, e.g. from a file cache. */
+int steps_ctx_set_tuned(steps_ctx *ctx, int64_t n, const steps_tile *tile);
 /* The shape the context would use for n particles in its precision. */
 int steps_ctx_get_tile(steps_ctx *ctx, int64_t n, steps_tile *out);
 /* Wait until all work enqueued on the context has finished; reports device
@@ -154,6 +159,17 @@ int steps_forces_ctx(steps_ctx *ctx, const double *pos, const double *mass,
 int steps_forces(const double *pos, const double *mass, const double *soft,
                  int64_t n, double *acc);
 
+/* Autotuner: time the compiled force kernels of the context's precision on
+ * these arrays -- i-particles per lane r in {1, 2, 4}, both the culled
+ * (spatially sorted) and the plain variant, and three j-splits around the
+ * heuristic's -- one force evaluation each, and keep the fastest for this n:
+ * later calls with the same n and precision use it unless a tile is forced.
+ * acc [3][n] is scratch output (holds S on return).  Synchronous.  *out
+ * receives the chosen shape. */
+int steps_autotune(steps_ctx *ctx, const double *pos, const double *mass,
+                   const double *soft, int64_t n, double *acc,
+                   steps_tile *out);
+
 /* ---- softened potential (diagnostic) ---------------------------------- */
 /* phi_i <- sum_{j != i, r_ij > 0} m_j phi(r_ij, h_i + h_j), G-free, with
  * phi the potential of the Eq. 4 kernel (phi = -1/r for r >= h,
@@ -162,6 +178,24 @@ int steps_potential_ctx(steps_ctx *ctx, const double *pos, const double *mass,
                         const double *soft, int64_t n, double *phi);
 int steps_potential(const double *pos, const double *mass, const double *soft,
                     int64_t n, double *phi);
+
+/* ---- comoving energies (diagnostic) ----------------------------------- */
+/* The paper gives no energy diagnostic; this one follows from Eq. 8.  With
+ * p = m a^2 dx/dt, Eq. 8 is dp/dt = -grad U_c / a for
+ *   U_c = (G/2) sum_{i != j} m_i m_j phi(r_ij, h_i + h_j)
+ *         - (Omega_m H0^2 / 4) sum_i m_i |x_i|^2,
+ * so K = (1/2) sum m a^2 |v|^2 and W = U_c / a obey the cosmic energy
+ * equation d(K + W)/dt = -H (2K + W) (Layzer-Irvine).
+ * out[7] (HOST): K, W, the pair part of U_c, the radial part, and
+ * sum m a^2 v (3 components).  vel [3][n] device.  FP64, O(N^2) (computes
+ * the softened potential), waits for the result.  In STEPS_NEWTONIAN_TEST
+ * mode a is taken as 1 and there is no radial part. */
+int steps_energy_ctx(steps_ctx *ctx, const double *pos, const double *vel,
+                     const double *mass, const double *soft, int64_t n,
+                     double a, const steps_cosmology *cosmo, double *out);
+int steps_energy(const double *pos, const double *vel, const double *mass,
+                 const double *soft, int64_t n, double a,
+                 const steps_cosmology *cosmo, double *out);
 
 /* ---- one KDK step: Sec. 2.3 Eqs. 9-11 with the acceleration of Eq. 8 --- */
 /* Advance pos, vel from scale factor a to a + da (in STEPS_NEWTONIAN_TEST
@@ -235,7 +269,11 @@ typedef struct steps_batch {
  * non-monotone offsets, N > 2^30, overlapping arrays, unknown flags. */
 int steps_batch_run(steps_ctx *ctx, const steps_batch *batch,
                     int32_t *member_status);
-/* Launch shape of the last steps_batch_run on this context. */
+/* The ensemble kernel is the context's forced tile (steps_ctx_set_tile;
+ * its r, tj and variant must name an ensemble kernel of the precision, else
+ * STEPS_E_INVAL, and STEPS_BATCH_AUTOTUNE then has no choice to make), or
+ * the fastest one under STEPS_BATCH_AUTOTUNE, or a default.
+ * Launch shape of the last steps_batch_run on this context: */
 int steps_batch_tile(steps_ctx *ctx, steps_tile *out);
 
 /* ---- background helpers (host only, no device work) ------------------- */

@@ -51,10 +51,12 @@ STEPS_NEWTONIAN_TEST = 1
 EXPORTS = (
     "steps_version", "steps_last_error", "steps_ctx_create",
     "steps_ctx_destroy", "steps_ctx_set_stream", "steps_ctx_set_precision",
-    "steps_ctx_set_flags", "steps_ctx_set_tile", "steps_ctx_get_tile",
-    "steps_sync", "steps_ctx_force_timing", "steps_forces_ctx",
+    "steps_ctx_set_flags", "steps_ctx_set_tile", "steps_ctx_set_tuned",
+    "steps_ctx_get_tile",
+    "steps_sync", "steps_ctx_force_timing", "steps_autotune", "steps_forces_ctx",
     "steps_forces", "steps_potential_ctx", "steps_potential",
-    "steps_step_ctx", "steps_step", "steps_batch_run", "steps_batch_tile",
+    "steps_step_ctx", "steps_step", "steps_energy_ctx", "steps_energy",
+    "steps_batch_run", "steps_batch_tile",
     "steps_hubble", "steps_dt", "steps_G", "steps_kms_to_mpc_per_gyr",
 )
 
@@ -144,15 +146,21 @@ def load():
             "steps_ctx_set_flags": ([vp, u32], i32),
             "steps_ctx_set_tile": ([vp, pt], i32),
             "steps_ctx_get_tile": ([vp, i64, pt], i32),
+            "steps_ctx_set_tuned": ([vp, i64, pt], i32),
             "steps_sync": ([vp], i32),
             "steps_ctx_force_timing": ([vp, ctypes.POINTER(d),
                                         ctypes.POINTER(i64), i32], i32),
+            "steps_autotune": ([vp, vp, vp, vp, i64, vp, pt], i32),
             "steps_forces_ctx": ([vp, vp, vp, vp, i64, vp], i32),
             "steps_forces": ([vp, vp, vp, i64, vp], i32),
             "steps_potential_ctx": ([vp, vp, vp, vp, i64, vp], i32),
             "steps_potential": ([vp, vp, vp, i64, vp], i32),
             "steps_step_ctx": ([vp, vp, vp, vp, vp, i64, vp, d, d, pc], i32),
             "steps_step": ([vp, vp, vp, vp, i64, vp, d, d, pc], i32),
+            "steps_energy_ctx": ([vp, vp, vp, vp, vp, i64, d, pc,
+                                  ctypes.POINTER(d)], i32),
+            "steps_energy": ([vp, vp, vp, vp, i64, d, pc, ctypes.POINTER(d)],
+                             i32),
             "steps_batch_run": ([vp, ctypes.POINTER(steps_batch),
                                  ctypes.POINTER(ctypes.c_int32)], i32),
             "steps_batch_tile": ([vp, pt], i32),
@@ -254,6 +262,11 @@ class Context:
         t = steps_tile(int(r), int(tj), int(jsplit), int(variant))
         _check(self._lib.steps_ctx_set_tile(self.handle, ctypes.byref(t)))
 
+    def set_tuned(self, n: int, r, tj, jsplit, variant=0):
+        """Record a tuned shape for n in this precision (steps_ctx_set_tuned)."""
+        t = steps_tile(int(r), int(tj), int(jsplit), int(variant))
+        _check(self._lib.steps_ctx_set_tuned(self.handle, int(n), ctypes.byref(t)))
+
     def get_tile(self, n: int):
         t = steps_tile()
         _check(self._lib.steps_ctx_get_tile(self.handle, int(n), ctypes.byref(t)))
@@ -320,6 +333,49 @@ def steps_forces(pos, mass, soft, acc=None, ctx: Context | None = None):
     return acc
 
 
+def _cache_key(ctx: Context, n: int) -> str:
+    import torch
+    name = torch.cuda.get_device_properties(ctx.device).name
+    return "%s|%s|%d|%d" % (name, steps_version(), ctx.precision, n)
+
+
+def steps_autotune(pos, mass, soft, ctx: Context, acc=None, cache=None):
+    """Time the compiled force kernels on these arrays and keep the fastest
+    for this n in ctx (see steps.h).  Returns the chosen tile.
+
+    cache: optional path of a JSON file keyed by (device name, library
+    version, precision, n).  A hit is recorded in ctx with
+    steps_ctx_set_tuned and nothing is timed; a miss is tuned and written
+    back."""
+    import json
+    import os
+    import torch
+    n = _n_of(mass)
+    table = {}
+    if cache is not None and os.path.exists(cache):
+        with open(cache) as f:
+            table = json.load(f)
+        hit = table.get(_cache_key(ctx, n))
+        if hit is not None:
+            ctx.set_tuned(n, hit["r"], hit["tj"], hit["jsplit"], hit["variant"])
+            return dict(hit)
+    if acc is None:
+        acc = torch.empty((3, n), dtype=torch.float64, device=pos.device)
+    t = steps_tile()
+    args = (_dev(pos, "pos", (3, n)), _dev(mass, "mass", (n,)),
+            _dev(soft, "soft", (n,)), n, _dev(acc, "acc", (3, n)))
+    ctx.bind_stream()
+    _check(ctx._lib.steps_autotune(ctx.handle, *args, ctypes.byref(t)))
+    out = {"r": t.r, "tj": t.tj, "jsplit": t.jsplit, "variant": t.variant}
+    if cache is not None:
+        table[_cache_key(ctx, n)] = out
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return out
+
+
 def steps_potential(pos, mass, soft, phi=None, ctx: Context | None = None):
     """phi <- G-free softened potential (FP64)."""
     import torch
@@ -345,6 +401,22 @@ def steps_step(pos, vel, mass, soft, acc, a, da, cosmo: Cosmology,
             _dev(acc, "acc", (3, n)), float(a), float(da), ctypes.byref(k))
     c.bind_stream()
     _check(c._lib.steps_step_ctx(c.handle, *args))
+
+
+def steps_energy(pos, vel, mass, soft, a, cosmo: Cosmology,
+                 ctx: Context | None = None):
+    """Comoving energies (see steps.h): dict K, W, U_pair, U_radial, P."""
+    n = _n_of(mass)
+    c = ctx or default_context(pos.device.index or 0)
+    out = (ctypes.c_double * 7)()
+    k = cosmo.to_c()
+    args = (_dev(pos, "pos", (3, n)), _dev(vel, "vel", (3, n)),
+            _dev(mass, "mass", (n,)), _dev(soft, "soft", (n,)), n, float(a),
+            ctypes.byref(k), out)
+    c.bind_stream()
+    _check(c._lib.steps_energy_ctx(c.handle, *args))
+    return {"K": out[0], "W": out[1], "U_pair": out[2], "U_radial": out[3],
+            "P": [out[4], out[5], out[6]]}
 
 
 def run(pos, vel, mass, soft, a_grid, cosmo: Cosmology, ctx=None, acc=None):

@@ -4,7 +4,8 @@
 
 Every HIP translation unit is compiled with packed FP32 disabled
 (-target-feature -packed-fp32-ops): the force kernels' FP32 arithmetic uses
-plain v_fma/v_mul/v_add_f32.
+plain v_fma/v_mul/v_add_f32.  MFMA results are kept in VGPRs
+(-amdgpu-mfma-vgpr-form), not accumulation registers.
 """
 from __future__ import annotations
 
@@ -26,6 +27,9 @@ SOURCES = ["steps_force.hip", "steps_sort.hip", "steps_batch.hip",
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in ordinary VGPRs: the FP64 pair kernel feeds each
+    # MFMA result straight into vector ALU work
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-command-line-argument",
 ]
 

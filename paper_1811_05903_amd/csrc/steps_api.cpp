@@ -75,7 +75,10 @@ struct steps_ctx {
   Buffer part;     // j-split partial sums
   Buffer shadow;   // FP32 shadow of the inputs
   Buffer arena;    // spatial-sort scratch (keys, permutation, sorted copy)
+  Buffer diag;     // energy diagnostic: potential and reduction partials
   steps_tile batch_tile = {0, 0, 0, 0};  // shape of the last ensemble run
+  // shapes found by steps_autotune: (kernel class, n) -> tile
+  std::vector<std::pair<std::pair<int, int64_t>, steps_tile>> tuned;
   int *flag = nullptr;  // device int for the finite check
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
   std::vector<hipEvent_t> prof_pool;
@@ -183,6 +186,11 @@ int variant_tj(int cls, int r) {
 steps_tile choose_tile(const steps_ctx *c, int64_t n) {
   const int cls = prec_class(c->precision);
   steps_tile t;
+  for (const auto &e : c->tuned) {
+    if (!c->tile_forced && e.first.first == cls && e.first.second == n) {
+      return e.second;
+    }
+  }
   if (c->tile_forced) {
     t = c->tile;
   } else {
@@ -360,6 +368,34 @@ int run_forces(steps_ctx *c, const double *pos, const double *mass,
   return STEPS_OK;
 }
 
+// Enqueue phi <- G-free softened potential (FP64, unsorted kernel r=2,
+// tj=128, j-split to ~2048 workgroups).  Arguments validated.
+int run_potential(steps_ctx *c, const double *pos, const double *mass,
+                  const double *soft, int n, double *phi) {
+  constexpr int R = 2, TJ = 128;
+  const int64_t nb = (n + 256LL * R - 1) / (256LL * R);
+  int64_t want = std::min<int64_t>((2048 + nb - 1) / nb,
+                                   std::max<int64_t>(1, n / (2 * TJ)));
+  int chunk = 0, js = 1;
+  split_j(n, TJ, (int)std::max<int64_t>(1, std::min<int64_t>(want, 1024)),
+          &chunk, &js);
+  double *out = phi;
+  if (js > 1) {
+    int rc = ensure(c, c->part, (size_t)js * (size_t)n * sizeof(double),
+                    "partial-sum");
+    if (rc) return rc;
+    out = (double *)c->part.p;
+  }
+  hipError_t e = steps::launch_potential(pos, mass, soft, n, chunk, js, out,
+                                         c->stream);
+  if (e != hipSuccess) return hip_fail(e, "potential kernel launch");
+  if (js > 1) {
+    e = steps::launch_reduce_partials1(out, js, n, phi, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
+  }
+  return STEPS_OK;
+}
+
 int check_finite(steps_ctx *c, std::initializer_list<std::pair<const double *, int64_t>> arrays) {
   if (!(c->flags & STEPS_CHECK_FINITE)) return STEPS_OK;
   hipError_t e = hipMemsetAsync(c->flag, 0, sizeof(int), c->stream);
@@ -501,6 +537,7 @@ int steps_ctx_destroy(steps_ctx *c) {
   if (c->part.p) (void)hipFree(c->part.p);
   if (c->shadow.p) (void)hipFree(c->shadow.p);
   if (c->arena.p) (void)hipFree(c->arena.p);
+  if (c->diag.p) (void)hipFree(c->diag.p);
   if (c->flag) (void)hipFree(c->flag);
   delete c;
   return rc;
@@ -559,6 +596,31 @@ int steps_ctx_set_tile(steps_ctx *c, const steps_tile *t) {
   return STEPS_OK;
 }
 
+int steps_ctx_set_tuned(steps_ctx *c, int64_t n, const steps_tile *t) {
+  if (!c || !t) return fail(STEPS_E_INVAL, "ctx or tile is NULL");
+  int rc = check_n(n);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(c->mu);
+  const int cls = prec_class(c->precision);
+  if (!steps::find_force_variant(cls, t->r, t->tj, t->variant)) {
+    return fail(STEPS_E_INVAL,
+                "no compiled force kernel with r=%d tj=%d variant=%d for this "
+                "precision",
+                t->r, t->tj, t->variant);
+  }
+  if (t->jsplit < 1 || t->jsplit > 1024) {
+    return fail(STEPS_E_INVAL, "jsplit must be in [1, 1024]");
+  }
+  for (auto &e : c->tuned) {
+    if (e.first.first == cls && e.first.second == n) {
+      e.second = *t;
+      return STEPS_OK;
+    }
+  }
+  c->tuned.push_back({{cls, n}, *t});
+  return STEPS_OK;
+}
+
 int steps_ctx_get_tile(steps_ctx *c, int64_t n, steps_tile *out) {
   if (!c || !out) return fail(STEPS_E_INVAL, "ctx or out is NULL");
   int rc = check_n(n);
@@ -614,6 +676,86 @@ int steps_forces_ctx(steps_ctx *c, const double *pos, const double *mass,
   return run_forces(c, pos, mass, soft, (int)n, acc);
 }
 
+int steps_autotune(steps_ctx *c, const double *pos, const double *mass,
+                   const double *soft, int64_t n, double *acc,
+                   steps_tile *out) {
+  if (!c || !out) return fail(STEPS_E_INVAL, "ctx or out is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  int rc = check_force_args(c, pos, mass, soft, n, acc,
+                            3 * (size_t)n * sizeof(double), "acc");
+  if (rc) return rc;
+  const int cls = prec_class(c->precision);
+  c->tuned.erase(std::remove_if(c->tuned.begin(), c->tuned.end(),
+                                [&](const auto &e) {
+                                  return e.first.first == cls &&
+                                         e.first.second == n;
+                                }),
+                 c->tuned.end());
+  const bool was_forced = c->tile_forced;
+  const steps_tile was_tile = c->tile;
+  c->tile_forced = false;
+  const steps_tile h = choose_tile(c, std::max<int64_t>(n, 1));
+  if (n == 0) {
+    *out = h;
+    c->tile_forced = was_forced;
+    return STEPS_OK;
+  }
+  // candidates: r in {1, 2, 4}; the heuristic's two variant choices of the
+  // class (FP64: 0 and 3, mixed: 0 and 2); jsplit h/2, h, 2h
+  std::vector<steps_tile> cands;
+  const int vars[2] = {0, cls == steps::kClassF64 ? 3 : 2};
+  for (int r : {1, 2, 4}) {
+    const int tj = variant_tj(cls, r);
+    for (int var : vars) {
+      if (!steps::find_force_variant(cls, r, tj, var)) continue;
+      for (int js : {std::max(1, h.jsplit / 2), h.jsplit,
+                     std::min(1024, 2 * h.jsplit)}) {
+        const steps_tile t = {r, tj, js, var};
+        bool dup = false;
+        for (const auto &q : cands) {
+          dup |= q.r == t.r && q.tj == t.tj && q.jsplit == t.jsplit &&
+                 q.variant == t.variant;
+        }
+        if (!dup) cands.push_back(t);
+      }
+    }
+  }
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  steps_tile best = h;
+  float best_ms = -1.0f;
+  // the heuristic shape first, also as a warm-up (scratch allocation)
+  c->tile = h;
+  c->tile_forced = true;
+  if (e == hipSuccess) rc = run_forces(c, pos, mass, soft, (int)n, acc);
+  for (size_t k = 0; e == hipSuccess && rc == STEPS_OK && k < cands.size(); ++k) {
+    c->tile = cands[k];
+    e = hipEventRecord(t0, c->stream);
+    if (e != hipSuccess) break;
+    rc = run_forces(c, pos, mass, soft, (int)n, acc);
+    if (rc) break;
+    e = hipEventRecord(t1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (e == hipSuccess && (best_ms < 0.0f || ms < best_ms)) {
+      best_ms = ms;
+      best = cands[k];
+    }
+  }
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  c->tile_forced = was_forced;
+  c->tile = was_tile;
+  if (e != hipSuccess) return hip_fail(e, "autotune timing");
+  if (rc) return rc;
+  c->tuned.push_back({{cls, n}, best});
+  *out = best;
+  return STEPS_OK;
+}
+
 int steps_forces(const double *pos, const double *mass, const double *soft,
                  int64_t n, double *acc) {
   int rc = STEPS_OK;
@@ -631,28 +773,69 @@ int steps_potential_ctx(steps_ctx *c, const double *pos, const double *mass,
                             (size_t)n * sizeof(double), "phi");
   if (rc || n == 0) return rc;
   if ((rc = check_finite(c, {{pos, 3 * n}, {mass, n}, {soft, n}}))) return rc;
-  constexpr int R = 2, TJ = 128;
-  const int64_t nb = (n + 256LL * R - 1) / (256LL * R);
-  int64_t want = std::min<int64_t>((2048 + nb - 1) / nb,
-                                   std::max<int64_t>(1, n / (2 * TJ)));
-  int chunk = 0, js = 1;
-  split_j(n, TJ, (int)std::max<int64_t>(1, std::min<int64_t>(want, 1024)),
-          &chunk, &js);
-  double *out = phi;
-  if (js > 1) {
-    rc = ensure(c, c->part, (size_t)js * (size_t)n * sizeof(double),
-                "partial-sum");
-    if (rc) return rc;
-    out = (double *)c->part.p;
+  return run_potential(c, pos, mass, soft, (int)n, phi);
+}
+
+int steps_energy_ctx(steps_ctx *c, const double *pos, const double *vel,
+                     const double *mass, const double *soft, int64_t n,
+                     double a, const steps_cosmology *cosmo, double *out) {
+  if (!c) return fail(STEPS_E_INVAL, "ctx is NULL");
+  if (!out) return fail(STEPS_E_INVAL, "out is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  int rc = validate_cosmo(cosmo);
+  if (rc) return rc;
+  const bool newton = cosmo->mode == STEPS_NEWTONIAN_TEST;
+  if (newton) a = 1.0;
+  if (!std::isfinite(a) || !(a > 0.0)) {
+    return fail(STEPS_E_INVAL, "a must be finite and > 0");
   }
-  hipError_t e = steps::launch_potential(pos, mass, soft, (int)n, chunk, js,
-                                         out, c->stream);
-  if (e != hipSuccess) return hip_fail(e, "potential kernel launch");
-  if (js > 1) {
-    e = steps::launch_reduce_partials1(out, js, (int)n, phi, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
+  if ((rc = check_force_args(c, pos, mass, soft, n, vel,
+                             3 * (size_t)n * sizeof(double), "vel"))) {
+    return rc;
   }
+  double sums[6] = {0, 0, 0, 0, 0, 0};
+  if (n > 0) {
+    if ((rc = check_finite(c, {{pos, 3 * n}, {vel, 3 * n}, {mass, n},
+                               {soft, n}}))) {
+      return rc;
+    }
+    Carve cv;
+    const size_t o_phi = cv.take((size_t)n * sizeof(double));
+    const size_t o_part = cv.take((size_t)steps::energy_blocks((int)n) * 6 * sizeof(double));
+    const size_t o_out = cv.take(6 * sizeof(double));
+    if ((rc = ensure(c, c->diag, cv.off, "energy"))) return rc;
+    char *base = (char *)c->diag.p;
+    double *phi = (double *)(base + o_phi);
+    if ((rc = run_potential(c, pos, mass, soft, (int)n, phi))) return rc;
+    hipError_t e = steps::launch_energy(pos, vel, mass, phi, (int)n,
+                                        (double *)(base + o_part),
+                                        (double *)(base + o_out), c->stream);
+    if (e != hipSuccess) return hip_fail(e, "energy kernel launch");
+    e = hipMemcpyAsync(sums, base + o_out, sizeof(sums), hipMemcpyDeviceToHost,
+                       c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "energy readback");
+  }
+  const steps::Background bg = make_background(cosmo);
+  const double a2 = a * a;
+  out[0] = a2 * sums[0];
+  out[2] = bg.g * sums[1];
+  out[3] = -0.5 * bg.radial() * sums[2];
+  out[1] = (out[2] + out[3]) / a;
+  out[4] = a2 * sums[3];
+  out[5] = a2 * sums[4];
+  out[6] = a2 * sums[5];
   return STEPS_OK;
+}
+
+int steps_energy(const double *pos, const double *vel, const double *mass,
+                 const double *soft, int64_t n, double a,
+                 const steps_cosmology *cosmo, double *out) {
+  int rc = STEPS_OK;
+  steps_ctx *c = default_ctx(&rc);
+  if (!c) return rc;
+  return steps_energy_ctx(c, pos, vel, mass, soft, n, a, cosmo, out);
 }
 
 int steps_potential(const double *pos, const double *mass, const double *soft,
@@ -1061,13 +1244,32 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
       if (bv[k].cls == R.cls) cands.push_back(&bv[k]);
     }
   }
-  // default: FP64 r=4 without the e^2 term, mixed r=2 (the single-run tuning)
-  for (const auto *v : cands) {
-    const bool want = R.cls == steps::kClassF64 ? (v->r == 4 && v->variant == 3)
-                                                : v->r == 2;
-    if (want) R.v = v;
+  if (c->tile_forced) {
+    // a shape forced on the context must name an ensemble kernel
+    for (const auto *v : cands) {
+      if (v->r == c->tile.r && v->tj == c->tile.tj &&
+          v->variant == c->tile.variant) {
+        R.v = v;
+      }
+    }
+    if (!R.v) {
+      return fail(STEPS_E_INVAL,
+                  "the forced tile (r=%d tj=%d variant=%d) names no ensemble "
+                  "kernel for this precision",
+                  c->tile.r, c->tile.tj, c->tile.variant);
+    }
+    cands.assign(1, R.v);  // nothing for STEPS_BATCH_AUTOTUNE to choose
+  } else {
+    // default: FP64 r=4 without the e^2 term, mixed r=2 (the single-run
+    // tuning)
+    for (const auto *v : cands) {
+      const bool want = R.cls == steps::kClassF64
+                            ? (v->r == 4 && v->variant == 3)
+                            : v->r == 2;
+      if (want) R.v = v;
+    }
+    if (!R.v) R.v = cands.front();
   }
-  if (!R.v) R.v = cands.front();
 
   // device memory
   size_t cub_bytes = 0;

@@ -282,6 +282,208 @@ __device__ __forceinline__ void force_block_f64(
 }
 
 // ---------------------------------------------------------------------------
+// One block's share, FP64, with both contractions of the far field on the
+// matrix cores.  Relative to a centre c (the j-tile's box centre), with
+// u = x - c and q = |u|^2, a pair's squared distance is a Gram product
+//   r_ij^2 = q_i + sum_k (-2 u_i, 1)_k (u_j, q_j)_k,
+// and the tile's contribution to S_i is a matrix product minus a rank-one
+// term,
+//   sum_j m_j r_ij^-3 (x_j - x_i) = sum_j w_ij (u_j) - u_i sum_j w_ij,
+// both sums being one product of the weight matrix with (m_j u_j, m_j).
+// v_mfma_f64_4x4x4_4b forms 4 blocks of (4 x 4) += (4 x 4)(4 x 4) per
+// wave, so one instruction yields r^2 for 64 pairs (16 i by 4 j) and a
+// second accumulates their weights; the vector ALU is left with the rsqrt
+// and four operations per pair.  The output lane layout of the first
+// product is the A-operand layout of the second, so the weights never
+// move between lanes.
+//
+// The Gram form loses about eps (|u_i| + |u_j|)^2 of r^2.  It is used only
+// for (wave, tile) blocks that are Newtonian (as in the culled kernels) and
+// well separated: |c_i - c_t| + |e_i| + |e_t| <= kSep * gap, where c, e are
+// the boxes' centres and half-diagonals and gap is their distance; then
+// the relative error of r^2 is below ~kSep^2 eps.  Other blocks take the
+// direct per-pair loop (one particle per lane, softening tested where the
+// boxes are near).  The wave owns 64 consecutive sorted particles.
+//
+// Lane roles of v_mfma_f64_4x4x4_4b on gfx950, lane l = n + 4 b + 16 k
+// for A (row n) and B (column n) with K index k, and l = n + 4 b + 16 m for
+// D (row m, column n), b the block.
+// ---------------------------------------------------------------------------
+constexpr double kSep = 4.0;
+
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int TJ>
+__device__ __forceinline__ void force_block_f64_mfma(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ soft, int stride, int i0, int iend, int jbeg,
+    int jend, const double *__restrict__ tinfo, double *__restrict__ out,
+    double2 *tile, double *gram, double *bmat) {
+  const int tid = threadIdx.x;
+  const int l = tid & 63;
+  const int wbase = i0 + (tid >> 6) * 64;
+  const int last = iend - 1;
+  const double *X = pos, *Y = pos + stride, *Z = pos + 2 * (size_t)stride;
+
+  // direct loop: lane l owns particle wbase + l
+  const bool valid = wbase + l < iend;
+  const int ip = min(wbase + l, last);
+  const double xi = X[ip], yi = Y[ip], zi = Z[ip], hi = soft[ip];
+  // matrix path: lane l is i-slot (l & 3) of block (l >> 2) & 3 in the
+  // operands (particle 16 r + (l & 15)), K index l >> 4, and holds component
+  // (l & 3) of particle 16 r + 4 ((l >> 2) & 3) + (l >> 4) in the output
+  const int kk = l >> 4, cc = l & 3;
+  const double *Pc = cc == 0 ? X : (cc == 1 ? Y : Z);
+  double gx[4], gy[4], gz[4], dc[4], sum[4], cmp[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ig = min(wbase + 16 * r + (l & 15), last);
+    gx[r] = X[ig];
+    gy[r] = Y[ig];
+    gz[r] = Z[ig];
+    const int id = min(wbase + 16 * r + 4 * ((l >> 2) & 3) + (l >> 4), last);
+    dc[r] = cc < 3 ? Pc[id] : 0.0;
+    sum[r] = cmp[r] = 0.0;
+  }
+  double wb[7];
+  {
+    const double xs[1] = {xi}, ys[1] = {yi}, zs[1] = {zi}, hs[1] = {hi};
+    const bool vs[1] = {valid};
+    wave_box<1, double>(xs, ys, zs, hs, vs, wb);
+  }
+  const double wc[3] = {0.5 * (wb[0] + wb[3]), 0.5 * (wb[1] + wb[4]),
+                        0.5 * (wb[2] + wb[5])};
+  const double we = 0.5 * sqrt((wb[3] - wb[0]) * (wb[3] - wb[0]) +
+                               (wb[4] - wb[1]) * (wb[4] - wb[1]) +
+                               (wb[5] - wb[2]) * (wb[5] - wb[2]));
+
+  for (int jt = jbeg; jt < jend; jt += TJ) {
+    const double *ti = tinfo + (size_t)((jt - jbeg) / TJ) * 8;
+    const double ct[3] = {0.5 * (ti[0] + ti[3]), 0.5 * (ti[1] + ti[4]),
+                          0.5 * (ti[2] + ti[5])};
+    __syncthreads();
+    for (int k = tid; k < TJ; k += kBlock) {
+      const int j = min(jt + k, jend - 1);
+      const double mj = (jt + k < jend) ? mass[j] : 0.0;
+      const double xj = X[j], yj = Y[j], zj = Z[j];
+      tile[3 * k] = double2{xj, yj};
+      tile[3 * k + 1] = double2{zj, mj};
+      tile[3 * k + 2] = double2{soft[j], 0.0};
+      const double ux = xj - ct[0], uy = yj - ct[1], uz = zj - ct[2];
+      const double mm = -1.5 * mj;
+      gram[4 * k] = ux;
+      gram[4 * k + 1] = uy;
+      gram[4 * k + 2] = uz;
+      gram[4 * k + 3] = fma(uz, uz, fma(uy, uy, ux * ux));
+      bmat[4 * k] = mm * ux;
+      bmat[4 * k + 1] = mm * uy;
+      bmat[4 * k + 2] = mm * uz;
+      bmat[4 * k + 3] = mm;
+    }
+    __syncthreads();
+
+    // box gap and separation, uniform over the wave
+    const double gxv = fmax(0.0, fmax(ti[0] - wb[3], wb[0] - ti[3]));
+    const double gyv = fmax(0.0, fmax(ti[1] - wb[4], wb[1] - ti[4]));
+    const double gzv = fmax(0.0, fmax(ti[2] - wb[5], wb[2] - ti[5]));
+    const double d2 = gxv * gxv + gyv * gyv + gzv * gzv;
+    const double hs = ti[6] + wb[6];
+    const bool far = d2 > fmax(hs * hs * (1.0 + 1e-6), 1e-30);
+    const double te = 0.5 * sqrt((ti[3] - ti[0]) * (ti[3] - ti[0]) +
+                                 (ti[4] - ti[1]) * (ti[4] - ti[1]) +
+                                 (ti[5] - ti[2]) * (ti[5] - ti[2]));
+    const double cd = sqrt((wc[0] - ct[0]) * (wc[0] - ct[0]) +
+                           (wc[1] - ct[1]) * (wc[1] - ct[1]) +
+                           (wc[2] - ct[2]) * (wc[2] - ct[2]));
+    const bool sep = far && (cd + we + te) <= kSep * sqrt(d2);
+    const bool use_mfma = __builtin_amdgcn_readfirstlane((int)sep) != 0;
+
+    double part[4];
+    if (use_mfma) {
+      double b1[4], qi[4], d2acc[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double ux = gx[r] - ct[0], uy = gy[r] - ct[1], uz = gz[r] - ct[2];
+        const double uk = kk == 0 ? ux : (kk == 1 ? uy : uz);
+        b1[r] = kk < 3 ? -2.0 * uk : 1.0;
+        qi[r] = fma(uz, uz, fma(uy, uy, ux * ux));
+        d2acc[r] = 0.0;
+      }
+      const int arow = 4 * (l & 3) + kk;  // gram[4 (4g + (l & 3)) + k]
+      const int brow = 4 * kk + cc;       // bmat[4 (4g + k) + c]
+#pragma unroll 2
+      for (int g = 0; g < TJ / 4; ++g) {
+        const double a1 = gram[16 * g + arow];
+        const double b2 = bmat[16 * g + brow];
+        double rr[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rr[r] = mfma4(a1, b1[r], qi[r]);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double y = __builtin_amdgcn_rsq(rr[r]);
+          const double y2 = y * y;
+          const double t = fma(rr[r], y2, -5.0 / 3.0);
+          const double w = (y * y2) * t;  // -(2/3) r^-3 (1 + 3/2 e)
+          d2acc[r] = mfma4(w, b2, d2acc[r]);
+        }
+      }
+      // column 3 holds sum_j m_j r^-3; subtract u_i times it
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double s3 = __shfl(d2acc[r], l | 3);
+        const double ctc = cc == 0 ? ct[0] : (cc == 1 ? ct[1] : ct[2]);
+        const double ui = cc < 3 ? dc[r] - ctc : 0.0;
+        part[r] = fma(-ui, s3, d2acc[r]);
+      }
+    } else {
+      double tx = 0.0, ty = 0.0, tz = 0.0;
+      if (__builtin_amdgcn_readfirstlane((int)far)) {
+#pragma unroll 4
+        for (int k = 0; k < TJ; ++k) {
+          const double2 a = tile[3 * k], b = tile[3 * k + 1];
+          const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          const double w = newton_w64<true>(r2, b.y);
+          tx = fma(w, dx, tx);
+          ty = fma(w, dy, ty);
+          tz = fma(w, dz, tz);
+        }
+      } else {
+#pragma unroll 2
+        for (int k = 0; k < TJ; ++k) {
+          const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
+          const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          const double h = c.x + hi;
+          double w = newton_w64<true>(r2, b.y);
+          if (r2 <= h * h) w = soft_w64(r2, h, b.y);
+          tx = fma(w, dx, tx);
+          ty = fma(w, dy, ty);
+          tz = fma(w, dz, tz);
+        }
+      }
+      // to the output layout: component cc of particle 16 r + 4 b + (l >> 4)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int src = 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
+        const double vx = __shfl(tx, src), vy = __shfl(ty, src), vz = __shfl(tz, src);
+        part[r] = cc == 0 ? vx : (cc == 1 ? vy : (cc == 2 ? vz : 0.0));
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) two_sum_add(sum[r], cmp[r], part[r]);
+  }
+
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int id = wbase + 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
+    if (cc < 3 && id < iend) out[(size_t)cc * stride + id] = sum[r] + cmp[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // One block's share, mixed precision: pair arithmetic in FP32 on an FP32
 // shadow [5][stride] (x, y, z, m, h); v_rsq_f32 (~2^-23) used as is.  Each
 // tile's FP32 partial is added into an FP64 accumulator, or into a
@@ -432,6 +634,22 @@ __global__ __launch_bounds__(kBlock) void k_force_f64(
       out + (size_t)blockIdx.y * 3 * (size_t)n, tile);
 }
 
+template <int TJ>
+__global__ __launch_bounds__(kBlock) void k_force_f64_mfma(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ soft, int n, int jchunk,
+    const double *__restrict__ tinfo, double *__restrict__ out) {
+  __shared__ double2 tile[3 * TJ];
+  __shared__ double gram[4 * TJ];
+  __shared__ double bmat[4 * TJ];
+  const int jbeg = blockIdx.y * jchunk;
+  force_block_f64_mfma<TJ>(pos, mass, soft, n, blockIdx.x * kBlock, n,
+                           jbeg, min(n, jbeg + jchunk),
+                           tinfo + (size_t)(jbeg / TJ) * 8,
+                           out + (size_t)blockIdx.y * 3 * (size_t)n, tile,
+                           gram, bmat);
+}
+
 template <int R, int TJ, bool KAHAN, bool CULL>
 __global__ __launch_bounds__(kBlock) void k_force_mixed(
     const float *__restrict__ shadow, int n, int jchunk,
@@ -476,6 +694,25 @@ __global__ __launch_bounds__(kBlock) void k_batch_force_f64(
   }
 }
 
+template <int TJ>
+__global__ __launch_bounds__(kBlock) void k_batch_force_f64_mfma(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ soft, int stride, const int4 *__restrict__ items,
+    const int *__restrict__ tbase, int nitems,
+    const double *__restrict__ tinfo, double *__restrict__ out, int *counter) {
+  __shared__ double2 tile[3 * TJ];
+  __shared__ double gram[4 * TJ];
+  __shared__ double bmat[4 * TJ];
+  __shared__ int slot;
+  for (int it = next_item(counter, &slot); it < nitems;
+       it = next_item(counter, &slot)) {
+    const int4 w = items[it];
+    force_block_f64_mfma<TJ>(pos, mass, soft, stride, w.x, w.y, w.z, w.w,
+                             tinfo + (size_t)tbase[it] * 8, out, tile, gram,
+                             bmat);
+  }
+}
+
 template <int R, int TJ, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_batch_force_mixed(
     const float *__restrict__ shadow, int stride, const int4 *__restrict__ items,
@@ -503,6 +740,14 @@ hipError_t launch_f64(const ForceLaunch &L, hipStream_t s) {
   dim3 grid(ceil_div(L.n, (long long)kBlock * R), L.jsplit);
   hipLaunchKernelGGL((k_force_f64<R, TJ, E2, CULL>), grid, dim3(kBlock), 0, s,
                      L.pos, L.mass, L.soft, L.n, L.jchunk, L.tinfo, L.out);
+  return hipGetLastError();
+}
+
+template <int TJ>
+hipError_t launch_f64_mfma(const ForceLaunch &L, hipStream_t s) {
+  dim3 grid(ceil_div(L.n, (long long)kBlock), L.jsplit);
+  hipLaunchKernelGGL((k_force_f64_mfma<TJ>), grid, dim3(kBlock), 0, s, L.pos,
+                     L.mass, L.soft, L.n, L.jchunk, L.tinfo, L.out);
   return hipGetLastError();
 }
 
@@ -544,6 +789,15 @@ hipError_t launch_batch_f64(const BatchLaunch &L, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int TJ>
+hipError_t launch_batch_f64_mfma(const BatchLaunch &L, hipStream_t s) {
+  static const int grid = persistent_grid(k_batch_force_f64_mfma<TJ>);
+  hipLaunchKernelGGL((k_batch_force_f64_mfma<TJ>), dim3(grid), dim3(kBlock), 0,
+                     s, L.pos, L.mass, L.soft, L.stride, L.items, L.tbase,
+                     L.nitems, L.tinfo, L.out, L.counter);
+  return hipGetLastError();
+}
+
 template <int R, int TJ>
 hipError_t launch_batch_mixed(const BatchLaunch &L, hipStream_t s) {
   if (L.kahan) {
@@ -561,7 +815,8 @@ hipError_t launch_batch_mixed(const BatchLaunch &L, hipStream_t s) {
 }
 
 // variant bits: 1 = FP64 weight without the e^2 term; 2 = sorted input with
-// (wave, tile) culling of the softening test.
+// (wave, tile) culling of the softening test; 4 = matrix-core far field
+// (with 2: sorted input; a wave owns 64 particles, so it is listed as r = 1).
 #define F64_SET(R)                                                  \
   {kClassF64, R, 128, 0, launch_f64<R, 128, true, false>},          \
       {kClassF64, R, 128, 1, launch_f64<R, 128, false, false>},     \
@@ -573,6 +828,7 @@ hipError_t launch_batch_mixed(const BatchLaunch &L, hipStream_t s) {
 
 const ForceVariant kVariants[] = {
     F64_SET(1),         F64_SET(2),         F64_SET(4),         F64_SET(8),
+    {kClassF64, 1, 128, 6, launch_f64_mfma<128>},
     MIXED_SET(1, 128),  MIXED_SET(2, 256),  MIXED_SET(4, 256),  MIXED_SET(8, 256),
 };
 
@@ -582,6 +838,7 @@ const BatchVariant kBatchVariants[] = {
     {kClassF64, 2, 128, 3, launch_batch_f64<2, 128, false>},
     {kClassF64, 4, 128, 2, launch_batch_f64<4, 128, true>},
     {kClassF64, 4, 128, 3, launch_batch_f64<4, 128, false>},
+    {kClassF64, 1, 128, 6, launch_batch_f64_mfma<128>},
     {kClassMixed, 1, 128, 2, launch_batch_mixed<1, 128>},
     {kClassMixed, 2, 256, 2, launch_batch_mixed<2, 256>},
     {kClassMixed, 4, 256, 2, launch_batch_mixed<4, 256>},

@@ -130,6 +130,13 @@ hipError_t launch_potential(const double *pos, const double *mass,
 hipError_t launch_reduce_partials1(const double *part, int jsplit, int n,
                                    double *phi, hipStream_t s);
 
+// Energy sums out[6] = (sum 1/2 m|v|^2, sum 1/2 m phi, sum m|x|^2,
+// sum m v_x, sum m v_y, sum m v_z); part holds energy_blocks(n) * 6 doubles.
+int energy_blocks(int n);
+hipError_t launch_energy(const double *pos, const double *vel,
+                         const double *mass, const double *phi, int n,
+                         double *part, double *out, hipStream_t s);
+
 // FP32 shadow [5][n] (x, y, z, m, h) from the FP64 inputs.
 hipError_t launch_shadow(const double *pos, const double *mass,
                          const double *soft, int n, float *shadow,

@@ -4,6 +4,8 @@
 // kernels of the KDK leapfrog (Sec. 2.3 Eqs. 9-11).  The pair-sum kernels
 // are in steps_force.hip, the spatial sort in steps_sort.hip.
 
+#include <algorithm>
+
 #include "steps_internal.h"
 
 namespace steps {
@@ -175,7 +177,66 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(
 // ---------------------------------------------------------------------------
 inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// Energy sums, 6 per block in a fixed order: sum 1/2 m |v|^2,
+// sum 1/2 m phi, sum m |x|^2, sum m v (3).  Grid-stride over particles,
+// then a fixed-shape tree within the block.
+constexpr int kEnergySums = 6;
+
+__global__ __launch_bounds__(kBlock) void k_energy_partial(
+    const double *__restrict__ pos, const double *__restrict__ vel,
+    const double *__restrict__ mass, const double *__restrict__ phi, int n,
+    double *__restrict__ part) {
+  __shared__ double red[kEnergySums][kBlock];
+  double v[kEnergySums] = {0, 0, 0, 0, 0, 0};
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += gridDim.x * kBlock) {
+    const double m = mass[i];
+    const double vx = vel[i], vy = vel[(size_t)n + i], vz = vel[2 * (size_t)n + i];
+    const double x = pos[i], y = pos[(size_t)n + i], z = pos[2 * (size_t)n + i];
+    v[0] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
+    v[1] += 0.5 * m * phi[i];
+    v[2] += m * (x * x + y * y + z * z);
+    v[3] += m * vx;
+    v[4] += m * vy;
+    v[5] += m * vz;
+  }
+#pragma unroll
+  for (int c = 0; c < kEnergySums; ++c) red[c][threadIdx.x] = v[c];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+#pragma unroll
+      for (int c = 0; c < kEnergySums; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kEnergySums) {
+    part[(size_t)blockIdx.x * kEnergySums + threadIdx.x] = red[threadIdx.x][0];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_energy_final(
+    const double *__restrict__ part, int nb, double *__restrict__ out) {
+  if (threadIdx.x < kEnergySums) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(size_t)b * kEnergySums + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
 }  // namespace
+
+int energy_blocks(int n) { return std::max(1, std::min(512, ceil_div(n, kBlock))); }
+
+hipError_t launch_energy(const double *pos, const double *vel,
+                         const double *mass, const double *phi, int n,
+                         double *part, double *out, hipStream_t s) {
+  const int nb = energy_blocks(n);
+  hipLaunchKernelGGL(k_energy_partial, dim3(nb), dim3(kBlock), 0, s, pos, vel,
+                     mass, phi, n, part);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kBlock), 0, s, part, nb, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_reduce_partials(const double *part, int jsplit, int n,
                                   double *acc, hipStream_t s) {

@@ -151,7 +151,7 @@ def test_batch_forces_match_oracle(st, prec):
     acc, offs = _zero_step_forces(st, members, ctx, st.STEPS_BATCH_AUTOTUNE)
     tile = st.steps_batch_tile(ctx)
     ctx.close()
-    assert tile["r"] in ((2, 4) if prec == "fp64" else (1, 2, 4))
+    assert tile["r"] in (1, 2, 4)
     for b, m in enumerate(members):
         if m.n < 2:
             continue
@@ -164,6 +164,36 @@ def test_batch_forces_match_oracle(st, prec):
             assert err.max() <= 1e-12
         else:
             assert np.median(err) <= 1e-5 and err.max() <= 1e-4
+
+
+# every FP64 ensemble kernel, forced through the context's tile: (r, tj,
+# variant) as listed by the library
+@pytest.mark.parametrize("shape", [(2, 128, 2), (2, 128, 3), (4, 128, 2),
+                                   (4, 128, 3), (1, 128, 6)])
+def test_batch_fp64_kernel_matches_oracle(st, shape):
+    members = _members()
+    ctx = st.Context(0, precision="fp64")
+    ctx.set_tile(shape[0], shape[1], 1, shape[2])
+    acc, offs = _zero_step_forces(st, members, ctx, st.STEPS_BATCH_AUTOTUNE)
+    tile = st.steps_batch_tile(ctx)
+    ctx.close()
+    assert (tile["r"], tile["tj"], tile["variant"]) == shape
+    for b, m in enumerate(members):
+        if m.n < 2:
+            continue
+        ref = oracle.forces(m.pos, m.mass, m.soft)
+        err = np.linalg.norm(acc[:, offs[b]:offs[b + 1]] - ref, axis=0) / \
+            np.linalg.norm(ref, axis=0)
+        assert err.max() <= 1e-12, (shape, b, err.max())
+
+
+def test_batch_forced_tile_must_name_an_ensemble_kernel(st):
+    members = _members()
+    ctx = st.Context(0, precision="fp64")
+    ctx.set_tile(8, 128, 1, 0)       # a single-run kernel only
+    with pytest.raises(st.StepsError):
+        _zero_step_forces(st, members, ctx)
+    ctx.close()
 
 
 def test_batch_mixed_trajectory_close_to_fp64(st):

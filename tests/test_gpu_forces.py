@@ -72,7 +72,7 @@ def _variants(st):
         ctx = st.Context(0, precision=prec)
         for r in (1, 2, 4, 8):
             for tj in (128, 256):
-                for var in (0, 1, 2, 3):
+                for var in (0, 1, 2, 3, 6):
                     for js in (1, 3, 7):
                         try:
                             ctx.set_tile(r, tj, js, var)
@@ -88,8 +88,9 @@ def test_every_launch_shape(st):
     pos, mass, soft = clustered(1537, 23, 0.1)
     ref = oracle.forces(pos, mass, soft)
     shapes = _variants(st)
-    # FP64: 4 r x 4 variants; mixed, Kahan: 4 r x 2 variants; 3 splits each
-    assert len(shapes) == (16 + 8 + 8) * 3
+    # FP64: 4 r x 4 variants + the matrix-core variant; mixed, Kahan: 4 r x 2
+    # variants; 3 splits each
+    assert len(shapes) == (17 + 8 + 8) * 3
     ctxs = {p: st.Context(0, precision=p) for p in ("fp64", "mixed", "kahan")}
     for prec, r, tj, var, js in shapes:
         ctx = ctxs[prec]
@@ -104,6 +105,49 @@ def test_every_launch_shape(st):
             assert err.max() <= 1e-3, (tag, err.max())
     for c in ctxs.values():
         c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotune_picks_a_compiled_shape_and_keeps_parity(st, prec, tmp_path):
+    ps = synth.config(2, n=40000)
+    ctx = st.Context(0, precision=prec)
+    p, m, h = dev(ps.pos), dev(ps.mass), dev(ps.soft)
+    cache = str(tmp_path / "tune.json")
+    tile = st.steps_autotune(p, m, h, ctx, cache=cache)
+    assert tile["r"] in (1, 2, 4) and tile["jsplit"] >= 1
+    assert ctx.get_tile(ps.n) == tile          # remembered for this n
+    # a fresh context restores the shape from the file without timing
+    ctx2 = st.Context(0, precision=prec)
+    assert st.steps_autotune(p, m, h, ctx2, cache=cache) == tile
+    assert ctx2.get_tile(ps.n) == tile
+    ctx2.close()
+    got = host(st.steps_forces(p, m, h, ctx=ctx))
+    ctx.close()
+    idx = np.random.default_rng(9).choice(ps.n, 64, replace=False)
+    err = rel_err(got[:, idx], oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx))
+    if prec == "fp64":
+        assert err.max() <= FP64_TOL
+    else:
+        assert np.median(err) <= 1e-5
+
+
+@pytest.mark.parametrize("n", [40000, None])
+def test_matrix_core_kernel_parity(st, n):
+    # the matrix-core FP64 kernel (variant 6) on stereographic sets large
+    # enough that most (wave, tile) blocks take the Gram path: all rows at
+    # n = 40000, 256 sampled rows at N = 2^18
+    ps = synth.config(2, n=n) if n else synth.config(2)
+    ctx = st.Context(0, precision="fp64")
+    ctx.set_tile(1, 128, 16, 6)
+    got = _gpu_forces(st, ps.pos, ps.mass, ps.soft, ctx)
+    again = _gpu_forces(st, ps.pos, ps.mass, ps.soft, ctx)
+    ctx.close()
+    assert np.array_equal(got, again)
+    idx = np.arange(ps.n) if n else \
+        np.random.default_rng(4).choice(ps.n, 256, replace=False)
+    err = rel_err(got[:, idx], oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx))
+    _report("fp64 matrix-core n=%d" % ps.n, err)
+    assert err.max() <= FP64_TOL
 
 
 def test_determinism_bitwise(st):
@@ -172,6 +216,23 @@ def test_full_size_config3_sampled_all_modes(st):
             assert err.max() <= FP64_TOL
         else:
             assert np.median(err) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_pair_momentum_vanishes(st, prec):
+    # Eq. 8's pair sum is antisymmetric (Newton's third law), so
+    # sum_i m_i S_i = 0 up to rounding; the bound is relative to the
+    # magnitude sum_i m_i |S_i|, on a clustered set that exercises every
+    # kernel branch and the culled fast loop.
+    pos, mass, soft = clustered(6000, 41, 0.1)
+    ctx = st.Context(0, precision=prec)
+    got = _gpu_forces(st, pos, mass, soft, ctx)
+    ctx.close()
+    net = np.abs((mass * got).sum(axis=1))
+    scale = (mass * np.abs(got)).sum(axis=1)
+    rel = (net / scale).max()
+    print("%s pair momentum %.3e" % (prec, rel), flush=True)
+    assert rel <= (1e-13 if prec == "fp64" else 1e-5)
 
 
 def test_potential_parity(st):

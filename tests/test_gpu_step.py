@@ -112,6 +112,46 @@ def test_comoving_reversibility(st):
     assert np.abs(host(v) - v0).max() < 1e-10 * vmax
 
 
+@pytest.mark.parametrize("newton", [False, True])
+def test_energy_parity(st, newton):
+    ps = synth.config(1, n=1500)
+    rng = np.random.default_rng(5)
+    vel = np.ascontiguousarray(rng.normal(0.0, 3.0, ps.pos.shape))
+    oc, gc = _pair(st, ps.cosmo, newtonian=newton)
+    ref = oracle.energy(ps.pos, vel, ps.mass, ps.soft, 0.3, oc)
+    got = st.steps_energy(dev(ps.pos), dev(vel), dev(ps.mass), dev(ps.soft), 0.3, gc)
+    for key in ("K", "W", "U_pair", "U_radial"):
+        assert got[key] == pytest.approx(ref[key], rel=1e-12, abs=1e-300), key
+    np.testing.assert_allclose(got["P"], ref["P"], rtol=1e-11,
+                               atol=1e-12 * np.abs(ref["P"]).max())
+
+
+def test_layzer_irvine_through_gpu_path(st):
+    # the oracle pins the residual at second order on this set; the GPU run
+    # must reproduce the oracle's residual curve
+    ps = synth.config(1, n=256)
+    vel = np.ascontiguousarray(np.random.default_rng(3).normal(0.0, 2.0, ps.pos.shape))
+    oc, gc = _pair(st, ps.cosmo)
+    grid = 0.05 * (0.06 / 0.05) ** (np.arange(21) / 20)
+    p, v, m, h = dev(ps.pos), dev(vel), dev(ps.mass), dev(ps.soft)
+    acc = st.steps_forces(p, m, h)
+    es = [st.steps_energy(p, v, m, h, grid[0], gc)]
+    for k in range(20):
+        st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], gc)
+        es.append(st.steps_energy(p, v, m, h, grid[k + 1], gc))
+    R = oracle.layzer_irvine(es, grid, oc)
+    po, vo = ps.pos.copy(), vel.copy()
+    So = oracle.forces(po, ps.mass, ps.soft)
+    eo = [oracle.energy(po, vo, ps.mass, ps.soft, grid[0], oc)]
+    for k in range(20):
+        oracle.kdk_step(po, vo, ps.mass, ps.soft, So, grid[k], grid[k + 1] - grid[k], oc)
+        eo.append(oracle.energy(po, vo, ps.mass, ps.soft, grid[k + 1], oc))
+    Ro = oracle.layzer_irvine(eo, grid, oc)
+    scale = max(abs(e["W"]) for e in eo)
+    assert np.abs(R - Ro).max() < 1e-8 * scale
+    assert np.abs(R).max() < 5e-2 * scale
+
+
 @pytest.mark.parametrize("prec", ["mixed", "kahan"])
 def test_mixed_step_close_to_fp64(st, prec):
     ps = synth.config(1, n=2048)
