@@ -148,10 +148,15 @@ def main():
                                                     args.precision, grid[0]),
                    "n": n, "precision": args.precision, "tile": tile,
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak,
+        # the FP64 matrix-core kernel and the vector kernels are both priced
+        # at the FP64 peak: on gfx950 dense FP64 MFMA and FP64 VALU share one
+        # 78.6 TFLOP/s pipe
+        "roofline": {"bound": "mfma" if force_kernel_name(args.precision, tile)
+                     .endswith("mfma") else "alu",
+                     "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic,
-                     "kernel": "k_force_%s" % ("f64" if args.precision == "fp64" else "mixed"),
+                     "kernel": force_kernel_name(args.precision, tile),
                      "kernel_ms": kern_ms,
                      "flop_per_pair": FLOP_PER_PAIR},
     }
@@ -204,14 +209,21 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def force_kernel_name(precision, tile):
+    """Name of the force kernel a launch shape runs (as rocprofv3 lists it)."""
+    if precision != "fp64":
+        return "k_force_mixed"
+    return "k_force_f64_mfma" if tile["variant"] & 4 else "k_force_f64"
+
+
 def profiled_traffic(precision, tile, workload):
     """HBM bytes per force launch from the committed rocprofv3 summary of
     this kernel and launch shape, or None if there is none or the kernel
     source has changed since it was taken."""
     import hashlib
-    cls = "f64" if precision == "fp64" else "mixed"
-    path = os.path.join(ROOT, "profiles", "k_force_%s_r%d_tj%d_v%d_workload%d.md"
-                        % (cls, tile["r"], tile["tj"], tile["variant"], workload))
+    path = os.path.join(ROOT, "profiles", "%s_r%d_tj%d_v%d_workload%d.md"
+                        % (force_kernel_name(precision, tile), tile["r"],
+                           tile["tj"], tile["variant"], workload))
     if not os.path.exists(path):
         return None
     traffic, ok = None, False

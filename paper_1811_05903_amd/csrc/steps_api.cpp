@@ -28,6 +28,7 @@ namespace {
 constexpr int64_t kMaxN = int64_t(1) << 30;
 // below this size the spatial sort costs more than the culling saves
 constexpr int64_t kSortMinN = 32768;
+constexpr int64_t kMfmaMinN = 131072;
 
 thread_local std::string t_err;
 
@@ -176,13 +177,28 @@ int variant_tj(int cls, int r) {
   return 0;
 }
 
-// Launch shape: a forced tile, else the heuristic, tuned on MI355X at
-// N = 2^18 and 2^21: FP64 r = 4, mixed r = 2 (fewer registers, more waves
-// to pair up FP32 issue); r is lowered for small n so that there are at
-// least 256 i-blocks where possible; the j range is then split so that the
-// grid holds about 8192 (FP64) or 16384 (mixed) workgroups, keeping every
-// split at least two tiles.  Culled (sorted) variants from kSortMinN up; in
-// FP64 the r^-3 correction stops at first order there (variant 3).
+// j-split for an (r, tj, variant) shape: enough splits that the grid holds
+// about 8192 (FP64 VALU), 16384 (mixed) or 65536 (FP64 matrix-core; its
+// blocks are a quarter the size) workgroups, keeping every split at least
+// two tiles.
+int heuristic_jsplit(int cls, int64_t n, int r, int tj, int variant) {
+  const int64_t nb = std::max<int64_t>(1, (n + 256LL * r - 1) / (256LL * r));
+  const int64_t target = cls != steps::kClassF64 ? 16384
+                         : (variant & steps::kVarMfma) ? 65536 : 8192;
+  int64_t js = (target + nb - 1) / nb;
+  js = std::min<int64_t>(js, std::max<int64_t>(1, n / (2LL * tj)));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(js, 1024));
+}
+
+// Launch shape: a forced tile, else a shape tuned for (class, n), else the
+// heuristic, measured on MI355X at N = 2^15 ... 2^21:
+//   * FP64 from kMfmaMinN up: the matrix-core kernel (variant 6, tj 256),
+//     5-7% ahead of the VALU kernel there and 7% behind it at 2^15;
+//   * otherwise FP64 r = 4, mixed r = 2 (fewer registers, more waves to pair
+//     up FP32 issue), r lowered for small n so that there are at least 256
+//     i-blocks where possible;
+//   * culled (sorted) variants from kSortMinN up; in FP64 the r^-3
+//     correction stops at first order there (variant 3).
 steps_tile choose_tile(const steps_ctx *c, int64_t n) {
   const int cls = prec_class(c->precision);
   steps_tile t;
@@ -191,24 +207,23 @@ steps_tile choose_tile(const steps_ctx *c, int64_t n) {
       return e.second;
     }
   }
-  if (c->tile_forced) {
-    t = c->tile;
+  if (c->tile_forced) return c->tile;
+  const bool f64 = cls == steps::kClassF64;
+  if (f64 && n >= kMfmaMinN) {
+    t.r = 1;
+    t.tj = 256;
+    t.variant = steps::kVarCull | steps::kVarMfma;
   } else {
-    const bool f64 = cls == steps::kClassF64;
     int r = f64 ? 4 : 2;
     while (r > 1 && (n + 256LL * r - 1) / (256LL * r) < 256) r /= 2;
     t.r = r;
     t.tj = variant_tj(cls, r);
-    const int64_t nb = std::max<int64_t>(1, (n + 256LL * r - 1) / (256LL * r));
-    const int64_t target = f64 ? 8192 : 16384;
-    int64_t js = (target + nb - 1) / nb;
-    js = std::min<int64_t>(js, std::max<int64_t>(1, n / (2LL * t.tj)));
-    t.jsplit = (int)std::max<int64_t>(1, std::min<int64_t>(js, 64));
     t.variant = 0;
     if (n >= kSortMinN) {
       t.variant = steps::kVarCull | (f64 ? steps::kVarNoE2 : 0);
     }
   }
+  t.jsplit = heuristic_jsplit(cls, n, t.r, t.tj, t.variant);
   return t;
 }
 
@@ -701,16 +716,22 @@ int steps_autotune(steps_ctx *c, const double *pos, const double *mass,
     c->tile_forced = was_forced;
     return STEPS_OK;
   }
-  // candidates: r in {1, 2, 4}; the heuristic's two variant choices of the
-  // class (FP64: 0 and 3, mixed: 0 and 2); jsplit h/2, h, 2h
+  // candidates: every compiled kernel of the class with r in {1, 2, 4}
+  // that the heuristic could choose (FP64 variants 0, 3 and 6, mixed 0 and
+  // 2), each at its heuristic j-split times 1/2, 1 and 2
   std::vector<steps_tile> cands;
-  const int vars[2] = {0, cls == steps::kClassF64 ? 3 : 2};
-  for (int r : {1, 2, 4}) {
-    const int tj = variant_tj(cls, r);
-    for (int var : vars) {
-      if (!steps::find_force_variant(cls, r, tj, var)) continue;
-      for (int js : {std::max(1, h.jsplit / 2), h.jsplit,
-                     std::min(1024, 2 * h.jsplit)}) {
+  int nvar = 0;
+  const steps::ForceVariant *vt = steps::force_variants(&nvar);
+  for (int q = 0; q < nvar; ++q) {
+    const steps::ForceVariant &v = vt[q];
+    const bool usable = cls == steps::kClassF64
+                            ? (v.variant == 0 || v.variant == 3 || v.variant == 6)
+                            : (v.variant == 0 || v.variant == 2);
+    if (v.cls != cls || !usable || (v.r != 1 && v.r != 2 && v.r != 4)) continue;
+    const int hj = heuristic_jsplit(cls, n, v.r, v.tj, v.variant);
+    {
+      const int r = v.r, tj = v.tj, var = v.variant;
+      for (int js : {std::max(1, hj / 2), hj, std::min(1024, 2 * hj)}) {
         const steps_tile t = {r, tj, js, var};
         bool dup = false;
         for (const auto &q : cands) {

@@ -295,21 +295,25 @@ __device__ __forceinline__ void force_block_f64(
 // second accumulates their weights; the vector ALU is left with the rsqrt
 // and four operations per pair.  The output lane layout of the first
 // product is the A-operand layout of the second, so the weights never
-// move between lanes.
+// move between lanes.  On gfx950 FP64 matrix and vector work share one
+// pipe (they do not co-issue), so the gain is only the operations saved:
+// per 64 pairs two MFMAs cost 8 vector slots and replace about 11.
 //
 // The Gram form loses about eps (|u_i| + |u_j|)^2 of r^2.  It is used only
 // for (wave, tile) blocks that are Newtonian (as in the culled kernels) and
 // well separated: |c_i - c_t| + |e_i| + |e_t| <= kSep * gap, where c, e are
-// the boxes' centres and half-diagonals and gap is their distance; then
-// the relative error of r^2 is below ~kSep^2 eps.  Other blocks take the
-// direct per-pair loop (one particle per lane, softening tested where the
-// boxes are near).  The wave owns 64 consecutive sorted particles.
+// the boxes' centres and half-diagonals and gap is their distance; then the
+// relative error of r^2 is below ~2 kSep^2 eps (8e-15 for kSep = 6, under
+// the first-order rsqrt residual that the VALU kernel accepts).  Other
+// blocks take the direct per-pair loop (one particle per lane, softening
+// tested where the boxes are near).  The wave owns 64 consecutive sorted
+// particles.
 //
 // Lane roles of v_mfma_f64_4x4x4_4b on gfx950, lane l = n + 4 b + 16 k
 // for A (row n) and B (column n) with K index k, and l = n + 4 b + 16 m for
 // D (row m, column n), b the block.
 // ---------------------------------------------------------------------------
-constexpr double kSep = 4.0;
+constexpr double kSep = 6.0;
 
 __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
@@ -829,6 +833,7 @@ hipError_t launch_batch_mixed(const BatchLaunch &L, hipStream_t s) {
 const ForceVariant kVariants[] = {
     F64_SET(1),         F64_SET(2),         F64_SET(4),         F64_SET(8),
     {kClassF64, 1, 128, 6, launch_f64_mfma<128>},
+    {kClassF64, 1, 256, 6, launch_f64_mfma<256>},
     MIXED_SET(1, 128),  MIXED_SET(2, 256),  MIXED_SET(4, 256),  MIXED_SET(8, 256),
 };
 

@@ -30,6 +30,7 @@ struct ForceLaunch {
 // variant bits of a force kernel
 constexpr int kVarNoE2 = 1;  // FP64: r^-3 correction to first order only
 constexpr int kVarCull = 2;  // sorted input, (wave, tile) softening culling
+constexpr int kVarMfma = 4;  // FP64 far field on the matrix cores (with kVarCull)
 
 struct ForceVariant {
   int cls;   // PrecClass

@@ -88,9 +88,9 @@ def test_every_launch_shape(st):
     pos, mass, soft = clustered(1537, 23, 0.1)
     ref = oracle.forces(pos, mass, soft)
     shapes = _variants(st)
-    # FP64: 4 r x 4 variants + the matrix-core variant; mixed, Kahan: 4 r x 2
+    # FP64: 4 r x 4 variants + two matrix-core tiles; mixed, Kahan: 4 r x 2
     # variants; 3 splits each
-    assert len(shapes) == (17 + 8 + 8) * 3
+    assert len(shapes) == (18 + 8 + 8) * 3
     ctxs = {p: st.Context(0, precision=p) for p in ("fp64", "mixed", "kahan")}
     for prec, r, tj, var, js in shapes:
         ctx = ctxs[prec]
@@ -131,14 +131,15 @@ def test_autotune_picks_a_compiled_shape_and_keeps_parity(st, prec, tmp_path):
         assert np.median(err) <= 1e-5
 
 
+@pytest.mark.parametrize("tj", [128, 256])
 @pytest.mark.parametrize("n", [40000, None])
-def test_matrix_core_kernel_parity(st, n):
+def test_matrix_core_kernel_parity(st, n, tj):
     # the matrix-core FP64 kernel (variant 6) on stereographic sets large
     # enough that most (wave, tile) blocks take the Gram path: all rows at
     # n = 40000, 256 sampled rows at N = 2^18
     ps = synth.config(2, n=n) if n else synth.config(2)
     ctx = st.Context(0, precision="fp64")
-    ctx.set_tile(1, 128, 16, 6)
+    ctx.set_tile(1, tj, 16, 6)
     got = _gpu_forces(st, ps.pos, ps.mass, ps.soft, ctx)
     again = _gpu_forces(st, ps.pos, ps.mass, ps.soft, ctx)
     ctx.close()
@@ -146,7 +147,7 @@ def test_matrix_core_kernel_parity(st, n):
     idx = np.arange(ps.n) if n else \
         np.random.default_rng(4).choice(ps.n, 256, replace=False)
     err = rel_err(got[:, idx], oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx))
-    _report("fp64 matrix-core n=%d" % ps.n, err)
+    _report("fp64 matrix-core tj=%d n=%d" % (tj, ps.n), err)
     assert err.max() <= FP64_TOL
 
 
