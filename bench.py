@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 5])
+    ap.add_argument("--li-study-only", action="store_true",
+                    help="workload 5: only the Layzer-Irvine step-convergence "
+                         "study at N = 2^17")
     ap.add_argument("--precision", default="fp64",
                     choices=["fp64", "mixed", "kahan"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -238,6 +241,50 @@ def profiled_traffic(precision, tile, workload):
     return traffic if ok else None
 
 
+def li_residual_run(st, dev, ps, nsteps, precision="fp64"):
+    """One run of the workload-5 recipe over a log-uniform grid of nsteps
+    from ps.a0 to ps.a1; returns |R| / |U_c(a1) - U_c(a0)| for the cosmic
+    energy equation in the form d[a (K + W)]/da = -K (K every step, W at the
+    two ends)."""
+    import numpy as np
+    c = ps.cosmo
+    cosmo = st.Cosmology(c.H0, c.omega_m, c.omega_l, c.omega_r)
+    grid = ps.a0 * (ps.a1 / ps.a0) ** (np.arange(nsteps + 1) / nsteps)
+    grid[-1] = ps.a1
+    ctx = st.Context(0, precision=precision)
+    p, v, m, h = dev(ps.pos), dev(ps.vel), dev(ps.mass), dev(ps.soft)
+    acc = st.steps_forces(p, m, h, ctx=ctx)
+    e0 = st.steps_energy(p, v, m, h, grid[0], cosmo, ctx=ctx)
+    kin, integral = e0["K"], 0.0
+    for k in range(nsteps):
+        st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], cosmo, ctx=ctx)
+        kn = st.steps_kinetic(v, m, grid[k + 1], ctx=ctx)["K"]
+        integral += 0.5 * (kin + kn) * (grid[k + 1] - grid[k])
+        kin = kn
+    e1 = st.steps_energy(p, v, m, h, grid[-1], cosmo, ctx=ctx)
+    ctx.close()
+    r = grid[-1] * (e1["K"] + e1["W"]) - grid[0] * (e0["K"] + e0["W"]) + integral
+    du = grid[-1] * e1["W"] - grid[0] * e0["W"]
+    return abs(r) / abs(du)
+
+
+def li_convergence(st, dev, n=131072, steps=(50, 100, 200, 400, 800)):
+    """Layzer-Irvine residual of the workload-5 recipe at a smaller N
+    against the number of steps: a second-order integrator shows the
+    residual falling ~4x per doubling once the steps resolve the dynamics."""
+    import synth
+    ps = synth.config(5, n=n)
+    out = []
+    for ns in steps:
+        t0 = time.perf_counter()
+        rel = li_residual_run(st, dev, ps, ns)
+        out.append({"steps": ns, "rel": rel})
+        log("Layzer-Irvine study n=%d steps=%d |R|/|dU_c| %.3e (%.1f s)"
+            % (n, ns, rel, time.perf_counter() - t0))
+    return {"n": n, "runs": out,
+            "ratios": [out[k]["rel"] / out[k + 1]["rel"] for k in range(len(out) - 1)]}
+
+
 def workload5(st, dev, args):
     """Workload 5: N = 2^22 (D = 500, r_max = 4000, LCDM 0.3089/0.6911/
     67.74, sigma 1%, Zel'dovich velocities), 50 log steps a 0.1 -> 1.0.
@@ -248,12 +295,15 @@ def workload5(st, dev, args):
     import numpy as np
     import torch
     import synth
+    study = li_convergence(st, dev)
+    if args.li_study_only:
+        return {"layzer_irvine_convergence": study}
     ps = synth.config(5)
     n, grid, c = ps.n, ps.a_grid(), ps.cosmo
     nsteps = min(args.steps if args.steps != 20 else 50, len(grid) - 1)
     cosmo = st.Cosmology(c.H0, c.omega_m, c.omega_l, c.omega_r)
     m, h = dev(ps.mass), dev(ps.soft)
-    every = 25   # energy (an O(N^2) FP64 potential) every this many steps
+    every = 25   # full energy (an O(N^2) FP64 potential) every this many steps
     log("workload 5: n=%d, %d steps a %.2f -> %.2f" % (n, nsteps, grid[0], grid[nsteps]))
     res = {}
     acc0 = {}
@@ -262,7 +312,8 @@ def workload5(st, dev, args):
         p, v = dev(ps.pos), dev(ps.vel)
         acc = st.steps_forces(p, m, h, ctx=ctx)
         acc0[prec] = acc.cpu().numpy()
-        es = [st.steps_energy(p, v, m, h, grid[0], cosmo, ctx=ctx)]
+        full = {0: st.steps_energy(p, v, m, h, grid[0], cosmo, ctx=ctx)}
+        kin = [full[0]["K"]]
         ctx.force_timing(reset=True)
         t_steps = 0.0
         for k in range(nsteps):
@@ -271,21 +322,28 @@ def workload5(st, dev, args):
             st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], cosmo, ctx=ctx)
             torch.cuda.synchronize()
             t_steps += time.perf_counter() - t0
+            kin.append(st.steps_kinetic(v, m, grid[k + 1], ctx=ctx)["K"])
             if (k + 1) % every == 0 or k + 1 == nsteps:
-                es.append(st.steps_energy(p, v, m, h, grid[k + 1], cosmo, ctx=ctx))
+                full[k + 1] = st.steps_energy(p, v, m, h, grid[k + 1], cosmo, ctx=ctx)
             log("%s step %d/%d a=%.4f (%.2f s/step)" % (prec, k + 1, nsteps, grid[k + 1], t_steps / (k + 1)))
         kms, cnt = ctx.force_timing(reset=True)
-        ks = [0] + [k for k in range(every, nsteps + 1, every)] + ([nsteps] if nsteps % every else [])
-        ga = [grid[k] for k in ks]
-        # trapezoid over the energy sample points
-        R, acc_int, e0 = [0.0], 0.0, es[0]["K"] + es[0]["W"]
-        for q in range(1, len(es)):
-            tt = st.steps_dt(cosmo, ga[q - 1], ga[q] - ga[q - 1])
-            f0 = st.steps_hubble(cosmo, ga[q - 1]) * (2 * es[q - 1]["K"] + es[q - 1]["W"])
-            f1 = st.steps_hubble(cosmo, ga[q]) * (2 * es[q]["K"] + es[q]["W"])
-            acc_int += 0.5 * (f0 + f1) * tt
-            R.append(es[q]["K"] + es[q]["W"] - e0 + acc_int)
-        wscale = max(abs(e["W"]) for e in es)
+        # cosmic energy equation in the scale factor, d[a (K + W)]/da = -K:
+        # R = a (K + W) - a0 (K0 + W0) + int K da, the integral by the
+        # trapezoid rule over every step (K is O(N) per step; W, which needs
+        # the O(N^2) potential, only at the sampled steps).  Relative to the
+        # change of U_c = a W since the start.
+        cum = [0.0]
+        for k in range(nsteps):
+            cum.append(cum[-1] + 0.5 * (kin[k] + kin[k + 1]) * (grid[k + 1] - grid[k]))
+        e0 = grid[0] * (full[0]["K"] + full[0]["W"])
+        li = []
+        for k in sorted(full):
+            if k == 0:
+                continue
+            r = grid[k] * (full[k]["K"] + full[k]["W"]) - e0 + cum[k]
+            du = grid[k] * full[k]["W"] - grid[0] * full[0]["W"]
+            li.append({"a": grid[k], "residual": r, "delta_U_c": du,
+                       "int_K_da": cum[k], "rel": abs(r) / abs(du)})
         pairs = float(n) * n
         res[prec] = {"steps": nsteps, "step_s": t_steps / nsteps,
                      "pairs_per_s": pairs * nsteps / t_steps,
@@ -294,8 +352,9 @@ def workload5(st, dev, args):
                      "tflops_20": FLOP_PER_PAIR * pairs / (kms / cnt * 1e-3) / 1e12,
                      "frac_peak": FLOP_PER_PAIR * pairs / (kms / cnt * 1e-3) / 1e12
                      / (FP64_PEAK_TF if prec == "fp64" else FP32_PEAK_TF),
-                     "layzer_irvine_a": ga, "layzer_irvine_rel": [r / wscale for r in R],
-                     "energies": [{"K": e["K"], "W": e["W"]} for e in es],
+                     "layzer_irvine": li,
+                     "energies": {str(k): {"a": grid[k], "K": e["K"], "W": e["W"]}
+                                  for k, e in sorted(full.items())},
                      "tile": ctx.get_tile(n)}
         res[prec + "_final_pos"] = p.cpu().numpy()
         ctx.close()
@@ -310,6 +369,7 @@ def workload5(st, dev, args):
                                   "mixed forces, FP64 kick/drift, a 0.1 -> 1.0" % n,
                       "n": n, "parallelism": "single GPU"},
            "mixed": res["mixed"], "fp64": res["fp64"],
+           "layzer_irvine_convergence": study,
            "mixed_vs_fp64_force_rel_err_start": {"median": float(np.median(ferr)),
                                                   "max": float(ferr.max())},
            "mixed_vs_fp64_final_dx_over_h": {"median": float(np.median(dpos)),
@@ -328,9 +388,10 @@ def workload5(st, dev, args):
                                "cores": oracle.num_threads(), "kind": "oracle",
                                "sample": "FP64 oracle pair sums for 4096 seeded-sampled "
                                          "i against all %d j (%.1f s)" % (n, tcpu)}
-    log("workload 5: mixed %.3e pairs/s, fp64 %.3e; LI drift mixed %.2e fp64 %.2e"
+    log("workload 5: mixed %.3e pairs/s, fp64 %.3e; Layzer-Irvine |R|/|dU_c| "
+        "at a=1: mixed %.2e fp64 %.2e"
         % (res["mixed"]["pairs_per_s"], res["fp64"]["pairs_per_s"],
-           abs(res["mixed"]["layzer_irvine_rel"][-1]), abs(res["fp64"]["layzer_irvine_rel"][-1])))
+           res["mixed"]["layzer_irvine"][-1]["rel"], res["fp64"]["layzer_irvine"][-1]["rel"]))
     return out
 
 

@@ -196,6 +196,16 @@ int steps_energy_ctx(steps_ctx *ctx, const double *pos, const double *vel,
 int steps_energy(const double *pos, const double *vel, const double *mass,
                  const double *soft, int64_t n, double a,
                  const steps_cosmology *cosmo, double *out);
+/* Kinetic part alone, O(N), no potential: out[4] (HOST) receives
+ * K = (1/2) sum m a^2 |v|^2 and sum m a^2 v.  vel [3][n], mass [n] device.
+ * Waits for the result.  With K at every step and the full energy at the
+ * two ends, the cosmic energy equation in the form
+ * d[a (K + W)]/da = -K can be checked without an O(N^2) potential per
+ * step. */
+int steps_kinetic_ctx(steps_ctx *ctx, const double *vel, const double *mass,
+                      int64_t n, double a, double *out);
+int steps_kinetic(const double *vel, const double *mass, int64_t n, double a,
+                  double *out);
 
 /* ---- one KDK step: Sec. 2.3 Eqs. 9-11 with the acceleration of Eq. 8 --- */
 /* Advance pos, vel from scale factor a to a + da (in STEPS_NEWTONIAN_TEST

@@ -56,6 +56,7 @@ EXPORTS = (
     "steps_sync", "steps_ctx_force_timing", "steps_autotune", "steps_forces_ctx",
     "steps_forces", "steps_potential_ctx", "steps_potential",
     "steps_step_ctx", "steps_step", "steps_energy_ctx", "steps_energy",
+    "steps_kinetic_ctx", "steps_kinetic",
     "steps_batch_run", "steps_batch_tile",
     "steps_hubble", "steps_dt", "steps_G", "steps_kms_to_mpc_per_gyr",
 )
@@ -161,6 +162,8 @@ def load():
                                   ctypes.POINTER(d)], i32),
             "steps_energy": ([vp, vp, vp, vp, i64, d, pc, ctypes.POINTER(d)],
                              i32),
+            "steps_kinetic_ctx": ([vp, vp, vp, i64, d, ctypes.POINTER(d)], i32),
+            "steps_kinetic": ([vp, vp, i64, d, ctypes.POINTER(d)], i32),
             "steps_batch_run": ([vp, ctypes.POINTER(steps_batch),
                                  ctypes.POINTER(ctypes.c_int32)], i32),
             "steps_batch_tile": ([vp, pt], i32),
@@ -417,6 +420,17 @@ def steps_energy(pos, vel, mass, soft, a, cosmo: Cosmology,
     _check(c._lib.steps_energy_ctx(c.handle, *args))
     return {"K": out[0], "W": out[1], "U_pair": out[2], "U_radial": out[3],
             "P": [out[4], out[5], out[6]]}
+
+
+def steps_kinetic(vel, mass, a, ctx: Context | None = None):
+    """Kinetic energy and peculiar momentum alone, O(N): dict K, P."""
+    n = _n_of(mass)
+    c = ctx or default_context(vel.device.index or 0)
+    out = (ctypes.c_double * 4)()
+    c.bind_stream()
+    _check(c._lib.steps_kinetic_ctx(c.handle, _dev(vel, "vel", (3, n)),
+                                    _dev(mass, "mass", (n,)), n, float(a), out))
+    return {"K": out[0], "P": [out[1], out[2], out[3]]}
 
 
 def run(pos, vel, mass, soft, a_grid, cosmo: Cosmology, ctx=None, acc=None):

@@ -850,6 +850,52 @@ int steps_energy_ctx(steps_ctx *c, const double *pos, const double *vel,
   return STEPS_OK;
 }
 
+int steps_kinetic_ctx(steps_ctx *c, const double *vel, const double *mass,
+                      int64_t n, double a, double *out) {
+  if (!c) return fail(STEPS_E_INVAL, "ctx is NULL");
+  if (!out) return fail(STEPS_E_INVAL, "out is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  if (!std::isfinite(a) || !(a > 0.0)) {
+    return fail(STEPS_E_INVAL, "a must be finite and > 0");
+  }
+  int rc = check_n(n);
+  if (rc) return rc;
+  double sums[6] = {0, 0, 0, 0, 0, 0};
+  if (n > 0) {
+    if ((rc = check_ptr(c, vel, 3 * (size_t)n * sizeof(double), "vel"))) return rc;
+    if ((rc = check_ptr(c, mass, (size_t)n * sizeof(double), "mass"))) return rc;
+    if ((rc = check_finite(c, {{vel, 3 * n}, {mass, n}}))) return rc;
+    Carve cv;
+    const size_t o_part = cv.take((size_t)steps::energy_blocks((int)n) * 6 * sizeof(double));
+    const size_t o_out = cv.take(6 * sizeof(double));
+    if ((rc = ensure(c, c->diag, cv.off, "energy"))) return rc;
+    char *base = (char *)c->diag.p;
+    hipError_t e = steps::launch_energy(nullptr, vel, mass, nullptr, (int)n,
+                                        (double *)(base + o_part),
+                                        (double *)(base + o_out), c->stream);
+    if (e != hipSuccess) return hip_fail(e, "energy kernel launch");
+    e = hipMemcpyAsync(sums, base + o_out, sizeof(sums), hipMemcpyDeviceToHost,
+                       c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "energy readback");
+  }
+  const double a2 = a * a;
+  out[0] = a2 * sums[0];
+  out[1] = a2 * sums[3];
+  out[2] = a2 * sums[4];
+  out[3] = a2 * sums[5];
+  return STEPS_OK;
+}
+
+int steps_kinetic(const double *vel, const double *mass, int64_t n, double a,
+                  double *out) {
+  int rc = STEPS_OK;
+  steps_ctx *c = default_ctx(&rc);
+  if (!c) return rc;
+  return steps_kinetic_ctx(c, vel, mass, n, a, out);
+}
+
 int steps_energy(const double *pos, const double *vel, const double *mass,
                  const double *soft, int64_t n, double a,
                  const steps_cosmology *cosmo, double *out) {

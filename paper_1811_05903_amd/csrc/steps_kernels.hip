@@ -192,10 +192,12 @@ __global__ __launch_bounds__(kBlock) void k_energy_partial(
        i += gridDim.x * kBlock) {
     const double m = mass[i];
     const double vx = vel[i], vy = vel[(size_t)n + i], vz = vel[2 * (size_t)n + i];
-    const double x = pos[i], y = pos[(size_t)n + i], z = pos[2 * (size_t)n + i];
     v[0] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
-    v[1] += 0.5 * m * phi[i];
-    v[2] += m * (x * x + y * y + z * z);
+    if (phi) v[1] += 0.5 * m * phi[i];
+    if (pos) {
+      const double x = pos[i], y = pos[(size_t)n + i], z = pos[2 * (size_t)n + i];
+      v[2] += m * (x * x + y * y + z * z);
+    }
     v[3] += m * vx;
     v[4] += m * vy;
     v[5] += m * vz;

@@ -126,6 +126,22 @@ def test_energy_parity(st, newton):
                                atol=1e-12 * np.abs(ref["P"]).max())
 
 
+def test_kinetic_matches_oracle_energy(st):
+    ps = synth.config(1, n=3001)
+    rng = np.random.default_rng(6)
+    vel = np.ascontiguousarray(rng.normal(0.0, 3.0, ps.pos.shape))
+    oc, _ = _pair(st, ps.cosmo)
+    ref = oracle.energy(ps.pos, vel, ps.mass, ps.soft, 0.45, oc)
+    got = st.steps_kinetic(dev(vel), dev(ps.mass), 0.45)
+    assert got["K"] == pytest.approx(ref["K"], rel=1e-13)
+    np.testing.assert_allclose(got["P"], ref["P"], rtol=1e-11,
+                               atol=1e-12 * np.abs(ref["P"]).max())
+    import torch
+    empty = torch.empty((3, 0), dtype=torch.float64, device="cuda")
+    assert st.steps_kinetic(empty, torch.empty(0, dtype=torch.float64,
+                                               device="cuda"), 1.0)["K"] == 0.0
+
+
 def test_layzer_irvine_through_gpu_path(st):
     # the oracle pins the residual at second order on this set; the GPU run
     # must reproduce the oracle's residual curve
