@@ -73,6 +73,10 @@ def _load():
         lib.oracle_energy.argtypes = [i64, vp, vp, vp, vp, d,
                                       ctypes.POINTER(_Cosmo), vp, i32]
         lib.oracle_energy.restype = i32
+        lib.oracle_adaptive_dt.argtypes = [i64, vp, vp, vp, vp, d,
+                                           ctypes.POINTER(_Cosmo), d, d,
+                                           ctypes.POINTER(d), ctypes.POINTER(d)]
+        lib.oracle_adaptive_dt.restype = i32
         lib.oracle_G.argtypes = []
         lib.oracle_G.restype = d
         lib.oracle_kms_to_mpc_per_gyr.argtypes = []
@@ -256,6 +260,47 @@ def layzer_irvine(energies, a_grid, cosmo: Cosmology):
         acc += 0.5 * (f0 + f1) * t
         out.append(energies[k]["K"] + energies[k]["W"] - e0 + acc)
     return np.array(out)
+
+
+def adaptive_dt(pos, vel, soft, S, a, cosmo: Cosmology, eps, dt_max):
+    """Global step of Eq. 12 at the current state (see oracle.c): returns
+    (dt, da), da being the scale-factor step whose cosmic time is dt."""
+    soft = np.ascontiguousarray(soft, dtype=np.float64)
+    n = soft.shape[0]
+    pos, vel, S = _soa(pos, n), _soa(vel, n), _soa(S, n)
+    c = cosmo._c()
+    dt, da = ctypes.c_double(), ctypes.c_double()
+    rc = _load().oracle_adaptive_dt(n, _ptr(pos), _ptr(vel), _ptr(soft),
+                                    _ptr(S), float(a), ctypes.byref(c),
+                                    float(eps), float(dt_max),
+                                    ctypes.byref(dt), ctypes.byref(da))
+    if rc:
+        raise ValueError("oracle_adaptive_dt: bad argument")
+    return dt.value, da.value
+
+
+def run_adaptive(pos, vel, mass, soft, a0, a1, cosmo: Cosmology, eps, dt_max,
+                 max_steps=100000, nthreads=0):
+    """Integrate from a0 to a1 with the step of Eq. 12 chosen before each
+    KDK step, the last one shortened to end exactly at a1 (a is the time
+    in the Newtonian test mode).  Copies its inputs; returns
+    (pos, vel, S, list of the scale factors reached)."""
+    n = mass.shape[0]
+    pos = _soa(pos, n).copy()
+    vel = _soa(vel, n).copy()
+    S = forces(pos, mass, soft, nthreads=nthreads)
+    a, grid = float(a0), [float(a0)]
+    for _ in range(max_steps):
+        if a >= a1:
+            break
+        _, da = adaptive_dt(pos, vel, soft, S, a, cosmo, eps, dt_max)
+        last = a + da >= a1
+        if last:
+            da = a1 - a
+        kdk_step(pos, vel, mass, soft, S, a, da, cosmo, nthreads)
+        a = a1 if last else a + da
+        grid.append(a)
+    return pos, vel, S, grid
 
 
 def run(pos, vel, mass, soft, a_grid, cosmo: Cosmology, nthreads=0):

@@ -46,6 +46,11 @@
  *     the half-step velocity in the second kick makes it first order).  The
  *     G-free pair sum S is carried between steps so that each step makes
  *     exactly one O(N^2) evaluation.
+ *   - The adaptive step of Eq. 12 is one global step, the smallest of the
+ *     particles' proposals, with eta_i = 2.8 h_i as printed (the text calls
+ *     it Plummer-equivalent although the spline's phi(0) = -2.8/h would make
+ *     that h/2.8; the printed factor is kept) and |A_i| the magnitude of the
+ *     kick's acceleration of Eq. 8 at the start of the step.
  *
  * Units: Mpc, Gyr, solar masses.  H0 is given in km/s/Mpc.
  */
@@ -337,6 +342,70 @@ int oracle_kdk_step(int64_t n, double *pos, double *vel, const double *mass,
   int rc = oracle_forces(n, pos, mass, soft, n, NULL, S, NULL, nthreads);
   if (rc) return rc;
   oracle_kick(n, pos, vel, S, a + da, 0.5 * dt, c, 1);
+  return 0;
+}
+
+/* ---- adaptive time step, Sec. 2.3 Eq. 12 ------------------------------ */
+
+/*
+ * Global step from the criterion of Eq. 12: particle i proposes
+ * sqrt(2 eta_i eps / |A_i|) with eta_i = 2.8 h_i (as printed), and the step
+ * is the smallest proposal, capped at dt_max.  A_i is the acceleration the
+ * kick of Eq. 9 applies -- the right-hand side of Eq. 8 -- at the start of
+ * the step: G S_i / a^3 + (Omega_m H0^2 / 2) x_i / a^3 - 2 H(a) v_i, with S
+ * the pair sum of the current positions.  A particle with A_i = 0 proposes
+ * no limit.  *da_out is the step in the scale factor whose cosmic-time
+ * interval (oracle_dt) equals *dt_out, found by bisection; in the Newtonian
+ * test mode A_i = G S_i and da = dt.  Returns 0, or -1 on a bad argument.
+ */
+int oracle_adaptive_dt(int64_t n, const double *pos, const double *vel,
+                       const double *soft, const double *S, double a,
+                       const oracle_cosmo *c, double eps, double dt_max,
+                       double *dt_out, double *da_out) {
+  if (n < 0 || !c || !dt_out || !da_out ||
+      (n > 0 && (!pos || !vel || !soft || !S))) {
+    return -1;
+  }
+  if (!(eps > 0.0) || !(dt_max > 0.0)) return -1;
+  if (!c->newtonian_test && !(a > 0.0)) return -1;
+  double ainv3 = 1.0, radial = 0.0, drag = 0.0;
+  if (!c->newtonian_test) {
+    double h0 = c->H0 * oracle_kms_to_mpc_per_gyr();
+    ainv3 = 1.0 / (a * a * a);
+    radial = 0.5 * c->omega_m * h0 * h0;
+    drag = 2.0 * oracle_hubble(a, c);
+  }
+  double dt = dt_max;
+  for (int64_t i = 0; i < n; ++i) {
+    double A2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      double x = pos[d * n + i], v = vel[d * n + i], s = S[d * n + i];
+      double Ad = c->G * s * ainv3 + radial * x * ainv3 - drag * v;
+      A2 += Ad * Ad;
+    }
+    if (A2 > 0.0) {
+      double eta = 2.8 * soft[i];
+      double prop = sqrt(2.0 * eta * eps / sqrt(A2));
+      if (prop < dt) dt = prop;
+    }
+  }
+  *dt_out = dt;
+  if (c->newtonian_test) {
+    *da_out = dt;
+    return 0;
+  }
+  /* bracket, then bisect: oracle_dt(a, .) increases with da */
+  double lo = 0.0, hi = a;
+  for (int k = 0; k < 200 && oracle_dt(a, hi, c) < dt; ++k) hi *= 2.0;
+  for (int k = 0; k < 200 && hi - lo > 1e-17 * hi; ++k) {
+    double mid = 0.5 * (lo + hi);
+    if (oracle_dt(a, mid, c) < dt) {
+      lo = mid;
+    } else {
+      hi = mid;
+    }
+  }
+  *da_out = 0.5 * (lo + hi);
   return 0;
 }
 
