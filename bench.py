@@ -268,7 +268,33 @@ def li_residual_run(st, dev, ps, nsteps, precision="fp64"):
     return abs(r) / abs(du)
 
 
-def li_convergence(st, dev, n=131072, steps=(50, 100, 200, 400, 800)):
+def li_adaptive_run(st, dev, ps, eps, dt_max=1e3, precision="fp64"):
+    """As li_residual_run, with the step of Eq. 12 (steps_adaptive_dt)
+    chosen before every step; returns (|R| / |dU_c|, steps taken)."""
+    c = ps.cosmo
+    cosmo = st.Cosmology(c.H0, c.omega_m, c.omega_l, c.omega_r)
+    ctx = st.Context(0, precision=precision)
+    p, v, m, h = dev(ps.pos), dev(ps.vel), dev(ps.mass), dev(ps.soft)
+    acc = st.steps_forces(p, m, h, ctx=ctx)
+    a, a1 = ps.a0, ps.a1
+    e0 = st.steps_energy(p, v, m, h, a, cosmo, ctx=ctx)
+    kin, integral, steps = e0["K"], 0.0, 0
+    while a < a1:
+        _, da = st.steps_adaptive_dt(p, v, h, acc, a, cosmo, eps, dt_max, ctx=ctx)
+        an = a1 if a + da >= a1 else a + da
+        st.steps_step(p, v, m, h, acc, a, an - a, cosmo, ctx=ctx)
+        kn = st.steps_kinetic(v, m, an, ctx=ctx)["K"]
+        integral += 0.5 * (kin + kn) * (an - a)
+        kin, a, steps = kn, an, steps + 1
+    e1 = st.steps_energy(p, v, m, h, a1, cosmo, ctx=ctx)
+    ctx.close()
+    r = a1 * (e1["K"] + e1["W"]) - ps.a0 * (e0["K"] + e0["W"]) + integral
+    du = a1 * e1["W"] - ps.a0 * e0["W"]
+    return abs(r) / abs(du), steps
+
+
+def li_convergence(st, dev, n=131072, steps=(50, 100, 200, 400, 800),
+                   eps=(3e-2, 1e-2, 3e-3)):
     """Layzer-Irvine residual of the workload-5 recipe at a smaller N
     against the number of steps: a second-order integrator shows the
     residual falling ~4x per doubling once the steps resolve the dynamics."""
@@ -281,8 +307,16 @@ def li_convergence(st, dev, n=131072, steps=(50, 100, 200, 400, 800)):
         out.append({"steps": ns, "rel": rel})
         log("Layzer-Irvine study n=%d steps=%d |R|/|dU_c| %.3e (%.1f s)"
             % (n, ns, rel, time.perf_counter() - t0))
+    adaptive = []
+    for e in eps:
+        t0 = time.perf_counter()
+        rel, ns = li_adaptive_run(st, dev, ps, e)
+        adaptive.append({"eps": e, "steps": ns, "rel": rel})
+        log("Layzer-Irvine study n=%d adaptive eps=%g: %d steps, |R|/|dU_c| %.3e (%.1f s)"
+            % (n, e, ns, rel, time.perf_counter() - t0))
     return {"n": n, "runs": out,
-            "ratios": [out[k]["rel"] / out[k + 1]["rel"] for k in range(len(out) - 1)]}
+            "ratios": [out[k]["rel"] / out[k + 1]["rel"] for k in range(len(out) - 1)],
+            "adaptive": adaptive}
 
 
 def workload5(st, dev, args):

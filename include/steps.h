@@ -232,6 +232,39 @@ int steps_step(double *pos, double *vel, const double *mass,
                const double *soft, int64_t n, double *acc, double a,
                double da, const steps_cosmology *cosmo);
 
+/* ---- adaptive step (Sec. 2.3, Eq. 12) --------------------------------- */
+/* The global step of Eq. 12 at the current state: particle i proposes
+ * sqrt(2 eta_i eps / |A_i|), eta_i = 2.8 h_i, with A_i the kick's
+ * acceleration of Eq. 8 at the start of the step,
+ *   A_i = G S_i / a^3 + (Omega_m H0^2 / 2) x_i / a^3 - 2 H(a) v_i
+ * (G S_i in the Newtonian test mode; a particle with A_i = 0 proposes no
+ * limit); *dt (HOST, Gyr) is the smallest proposal capped at dt_max, and
+ * *da (HOST) the scale-factor step whose cosmic-time interval is *dt (= dt
+ * in the Newtonian test mode).  pos, vel, acc [3][n] and soft [n] device;
+ * acc must hold S(pos), as steps_step leaves it.  eps and dt_max finite and
+ * > 0.  Waits for the result (one device min-reduction). */
+int steps_adaptive_dt_ctx(steps_ctx *ctx, const double *pos, const double *vel,
+                          const double *soft, const double *acc, int64_t n,
+                          double a, const steps_cosmology *cosmo, double eps,
+                          double dt_max, double *dt, double *da);
+int steps_adaptive_dt(const double *pos, const double *vel, const double *soft,
+                      const double *acc, int64_t n, double a,
+                      const steps_cosmology *cosmo, double eps, double dt_max,
+                      double *dt, double *da);
+/* Integrate from a0 to a1 (>= a0) with the step of Eq. 12 chosen before
+ * every KDK step, the last one shortened to end exactly at a1 (a is the time
+ * in the Newtonian test mode).  acc is output: S(pos) is computed first and
+ * S of the final positions is left in it.  At most max_steps steps;
+ * *steps_taken and *a_reached (HOST, may be NULL) report how far it got.
+ * Errors as steps_step and steps_adaptive_dt; on an error the state is that
+ * after the last completed step. */
+int steps_run_adaptive_ctx(steps_ctx *ctx, double *pos, double *vel,
+                           const double *mass, const double *soft, int64_t n,
+                           double *acc, double a0, double a1,
+                           const steps_cosmology *cosmo, double eps,
+                           double dt_max, int64_t max_steps,
+                           int64_t *steps_taken, double *a_reached);
+
 /* ---- ensembles of independent simulations ------------------------------ */
 /* The paper motivates fast simulations for fitting cosmological parameters
  * (abstract); an ensemble runs many small, independent StePS simulations of

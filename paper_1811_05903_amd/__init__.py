@@ -56,7 +56,8 @@ EXPORTS = (
     "steps_sync", "steps_ctx_force_timing", "steps_autotune", "steps_forces_ctx",
     "steps_forces", "steps_potential_ctx", "steps_potential",
     "steps_step_ctx", "steps_step", "steps_energy_ctx", "steps_energy",
-    "steps_kinetic_ctx", "steps_kinetic",
+    "steps_kinetic_ctx", "steps_kinetic", "steps_adaptive_dt_ctx",
+    "steps_adaptive_dt", "steps_run_adaptive_ctx",
     "steps_batch_run", "steps_batch_tile",
     "steps_hubble", "steps_dt", "steps_G", "steps_kms_to_mpc_per_gyr",
 )
@@ -163,6 +164,13 @@ def load():
             "steps_energy": ([vp, vp, vp, vp, i64, d, pc, ctypes.POINTER(d)],
                              i32),
             "steps_kinetic_ctx": ([vp, vp, vp, i64, d, ctypes.POINTER(d)], i32),
+            "steps_adaptive_dt_ctx": ([vp, vp, vp, vp, vp, i64, d, pc, d, d,
+                                       ctypes.POINTER(d), ctypes.POINTER(d)], i32),
+            "steps_adaptive_dt": ([vp, vp, vp, vp, i64, d, pc, d, d,
+                                   ctypes.POINTER(d), ctypes.POINTER(d)], i32),
+            "steps_run_adaptive_ctx": ([vp, vp, vp, vp, vp, i64, vp, d, d, pc,
+                                        d, d, i64, ctypes.POINTER(i64),
+                                        ctypes.POINTER(d)], i32),
             "steps_kinetic": ([vp, vp, i64, d, ctypes.POINTER(d)], i32),
             "steps_batch_run": ([vp, ctypes.POINTER(steps_batch),
                                  ctypes.POINTER(ctypes.c_int32)], i32),
@@ -431,6 +439,44 @@ def steps_kinetic(vel, mass, a, ctx: Context | None = None):
     _check(c._lib.steps_kinetic_ctx(c.handle, _dev(vel, "vel", (3, n)),
                                     _dev(mass, "mass", (n,)), n, float(a), out))
     return {"K": out[0], "P": [out[1], out[2], out[3]]}
+
+
+def steps_adaptive_dt(pos, vel, soft, acc, a, cosmo: Cosmology, eps, dt_max,
+                      ctx: Context | None = None):
+    """Step of Eq. 12 at the current state (acc = S(pos)): (dt, da)."""
+    n = _n_of(soft)
+    c = ctx or default_context(pos.device.index or 0)
+    k = cosmo.to_c()
+    dt, da = ctypes.c_double(), ctypes.c_double()
+    c.bind_stream()
+    _check(c._lib.steps_adaptive_dt_ctx(
+        c.handle, _dev(pos, "pos", (3, n)), _dev(vel, "vel", (3, n)),
+        _dev(soft, "soft", (n,)), _dev(acc, "acc", (3, n)), n, float(a),
+        ctypes.byref(k), float(eps), float(dt_max), ctypes.byref(dt),
+        ctypes.byref(da)))
+    return dt.value, da.value
+
+
+def steps_run_adaptive(pos, vel, mass, soft, a0, a1, cosmo: Cosmology, eps,
+                       dt_max, max_steps=1 << 40, acc=None,
+                       ctx: Context | None = None):
+    """Integrate in place from a0 to a1 with the step of Eq. 12; returns
+    (acc, steps taken, a reached)."""
+    import torch
+    n = _n_of(mass)
+    if acc is None:
+        acc = torch.empty((3, n), dtype=torch.float64, device=pos.device)
+    c = ctx or default_context(pos.device.index or 0)
+    k = cosmo.to_c()
+    steps, reached = ctypes.c_int64(), ctypes.c_double()
+    c.bind_stream()
+    _check(c._lib.steps_run_adaptive_ctx(
+        c.handle, _dev(pos, "pos", (3, n)), _dev(vel, "vel", (3, n)),
+        _dev(mass, "mass", (n,)), _dev(soft, "soft", (n,)), n,
+        _dev(acc, "acc", (3, n)), float(a0), float(a1), ctypes.byref(k),
+        float(eps), float(dt_max), int(max_steps), ctypes.byref(steps),
+        ctypes.byref(reached)))
+    return acc, steps.value, reached.value
 
 
 def run(pos, vel, mass, soft, a_grid, cosmo: Cosmology, ctx=None, acc=None):

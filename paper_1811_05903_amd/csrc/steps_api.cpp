@@ -913,12 +913,10 @@ int steps_potential(const double *pos, const double *mass, const double *soft,
   return steps_potential_ctx(c, pos, mass, soft, n, phi);
 }
 
-int steps_step_ctx(steps_ctx *c, double *pos, double *vel, const double *mass,
-                   const double *soft, int64_t n, double *acc, double a,
-                   double da, const steps_cosmology *cosmo) {
-  if (!c) return fail(STEPS_E_INVAL, "ctx is NULL");
-  std::lock_guard<std::mutex> lk(c->mu);
-  DeviceGuard g(c->device);
+// One KDK step; the caller holds the context lock and the device guard.
+static int step_impl(steps_ctx *c, double *pos, double *vel, const double *mass,
+                     const double *soft, int64_t n, double *acc, double a,
+                     double da, const steps_cosmology *cosmo) {
   int rc = validate_cosmo(cosmo);
   if (rc) return rc;
   if (!std::isfinite(a) || !std::isfinite(da)) {
@@ -974,6 +972,132 @@ int steps_step_ctx(steps_ctx *c, double *pos, double *vel, const double *mass,
                              rad * ai3_1, 1.0 / denom, c->stream);
   if (e != hipSuccess) return hip_fail(e, "kick kernel launch");
   return STEPS_OK;
+}
+
+int steps_step_ctx(steps_ctx *c, double *pos, double *vel, const double *mass,
+                   const double *soft, int64_t n, double *acc, double a,
+                   double da, const steps_cosmology *cosmo) {
+  if (!c) return fail(STEPS_E_INVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  return step_impl(c, pos, vel, mass, soft, n, acc, a, da, cosmo);
+}
+
+// Adaptive step of Eq. 12 at the current state; the caller holds the lock.
+static int adaptive_impl(steps_ctx *c, const double *pos, const double *vel,
+                         const double *soft, const double *acc, int64_t n,
+                         double a, const steps_cosmology *cosmo, double eps,
+                         double dt_max, double *dt_out, double *da_out) {
+  int rc = validate_cosmo(cosmo);
+  if (rc) return rc;
+  const bool newton = cosmo->mode == STEPS_NEWTONIAN_TEST;
+  if (!std::isfinite(a) || (!newton && !(a > 0.0))) {
+    return fail(STEPS_E_INVAL, "a must be finite (and > 0 unless Newtonian)");
+  }
+  if (!std::isfinite(eps) || !(eps > 0.0) || !std::isfinite(dt_max) ||
+      !(dt_max > 0.0)) {
+    return fail(STEPS_E_INVAL, "eps and dt_max must be finite and > 0");
+  }
+  if ((rc = check_n(n))) return rc;
+  double q = INFINITY;
+  if (n > 0) {
+    const size_t v3 = 3 * (size_t)n * sizeof(double), v1 = (size_t)n * sizeof(double);
+    if ((rc = check_ptr(c, pos, v3, "pos"))) return rc;
+    if ((rc = check_ptr(c, vel, v3, "vel"))) return rc;
+    if ((rc = check_ptr(c, soft, v1, "soft"))) return rc;
+    if ((rc = check_ptr(c, acc, v3, "acc"))) return rc;
+    if ((rc = check_finite(c, {{pos, 3 * n}, {vel, 3 * n}, {soft, n},
+                               {acc, 3 * n}}))) {
+      return rc;
+    }
+    Carve cv;
+    const size_t o_part = cv.take((size_t)steps::dt_blocks((int)n) * sizeof(double));
+    const size_t o_out = cv.take(sizeof(double));
+    if ((rc = ensure(c, c->diag, cv.off, "adaptive step"))) return rc;
+    char *base = (char *)c->diag.p;
+    const steps::Background bg = make_background(cosmo);
+    const double ai3 = newton ? 1.0 : 1.0 / (a * a * a);
+    hipError_t e = steps::launch_dt_min(pos, vel, acc, soft, (int)n,
+                                        bg.g * ai3, bg.radial() * ai3,
+                                        2.0 * bg.hubble(a),
+                                        (double *)(base + o_part),
+                                        (double *)(base + o_out), c->stream);
+    if (e != hipSuccess) return hip_fail(e, "adaptive step kernel launch");
+    e = hipMemcpyAsync(&q, base + o_out, sizeof(double), hipMemcpyDeviceToHost,
+                       c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "adaptive step readback");
+  }
+  double dt = dt_max;
+  if (std::isfinite(q)) dt = std::min(dt_max, std::sqrt(2.0 * eps * q));
+  double da = 0.0;
+  if (!make_background(cosmo).da_for_dt(a, dt, &da)) {
+    return fail(STEPS_E_INVAL, "no scale-factor step reaches dt = %g Gyr", dt);
+  }
+  *dt_out = dt;
+  *da_out = da;
+  return STEPS_OK;
+}
+
+int steps_adaptive_dt_ctx(steps_ctx *c, const double *pos, const double *vel,
+                          const double *soft, const double *acc, int64_t n,
+                          double a, const steps_cosmology *cosmo, double eps,
+                          double dt_max, double *dt, double *da) {
+  if (!c) return fail(STEPS_E_INVAL, "ctx is NULL");
+  if (!dt || !da) return fail(STEPS_E_INVAL, "dt or da is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  return adaptive_impl(c, pos, vel, soft, acc, n, a, cosmo, eps, dt_max, dt, da);
+}
+
+int steps_adaptive_dt(const double *pos, const double *vel, const double *soft,
+                      const double *acc, int64_t n, double a,
+                      const steps_cosmology *cosmo, double eps, double dt_max,
+                      double *dt, double *da) {
+  int rc = STEPS_OK;
+  steps_ctx *c = default_ctx(&rc);
+  if (!c) return rc;
+  return steps_adaptive_dt_ctx(c, pos, vel, soft, acc, n, a, cosmo, eps,
+                               dt_max, dt, da);
+}
+
+int steps_run_adaptive_ctx(steps_ctx *c, double *pos, double *vel,
+                           const double *mass, const double *soft, int64_t n,
+                           double *acc, double a0, double a1,
+                           const steps_cosmology *cosmo, double eps,
+                           double dt_max, int64_t max_steps,
+                           int64_t *steps_taken, double *a_reached) {
+  if (!c) return fail(STEPS_E_INVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  DeviceGuard g(c->device);
+  if (!std::isfinite(a0) || !std::isfinite(a1) || !(a1 >= a0)) {
+    return fail(STEPS_E_INVAL, "need finite a0 <= a1");
+  }
+  if (max_steps < 0) return fail(STEPS_E_INVAL, "max_steps < 0");
+  int rc = validate_cosmo(cosmo);
+  if (rc) return rc;
+  if ((rc = check_force_args(c, pos, mass, soft, n, acc,
+                             3 * (size_t)n * sizeof(double), "acc"))) {
+    return rc;
+  }
+  if (n > 0 && (rc = run_forces(c, pos, mass, soft, (int)n, acc))) return rc;
+  double a = a0;
+  int64_t k = 0;
+  while (a < a1 && k < max_steps) {
+    double dt = 0.0, da = 0.0;
+    if ((rc = adaptive_impl(c, pos, vel, soft, acc, n, a, cosmo, eps, dt_max,
+                            &dt, &da))) {
+      break;
+    }
+    const bool last = a + da >= a1;
+    if (last) da = a1 - a;
+    if ((rc = step_impl(c, pos, vel, mass, soft, n, acc, a, da, cosmo))) break;
+    a = last ? a1 : a + da;
+    ++k;
+  }
+  if (steps_taken) *steps_taken = k;
+  if (a_reached) *a_reached = a;
+  return rc;
 }
 
 int steps_step(double *pos, double *vel, const double *mass,

@@ -103,4 +103,27 @@ bool Background::step_dt(double a, double da, double *dt) const {
   return true;
 }
 
+bool Background::da_for_dt(double a, double dt, double *da) const {
+  if (newtonian_test) {
+    *da = dt;
+    return true;
+  }
+  if (!(dt > 0.0) || !(a > 0.0) || !(e2(a) > 0.0)) return false;
+  double x = dt * a * hubble(a);  // first-order start: da = a H dt
+  for (int it = 0; it < 60; ++it) {
+    double t = 0.0;
+    if (!(a + x > 0.0) || !step_dt(a, x, &t)) return false;
+    const double step = (t - dt) * (a + x) * hubble(a + x);
+    double nx = x - step;
+    if (!(nx > 0.0)) nx = 0.5 * x;  // stay on the positive side
+    if (std::fabs(nx - x) <= 1e-15 * nx) {
+      *da = nx;
+      return true;
+    }
+    x = nx;
+  }
+  *da = x;
+  return std::isfinite(x) && x > 0.0;
+}
+
 }  // namespace steps

@@ -20,6 +20,9 @@ struct Background {
   double hubble(double a) const;
   // cosmic time from a to a + da; false if H^2 <= 0 on the way
   bool step_dt(double a, double da, double *dt) const;
+  // the da > 0 whose step_dt is dt (> 0): Newton's method on step_dt, whose
+  // derivative in da is 1 / ((a + da) H(a + da)); false if it fails
+  bool da_for_dt(double a, double dt, double *da) const;
   // radial-term coefficient Omega_m H0^2 / 2 (the (4 pi G / 3) rho_bar of
   // Eq. 8 with rho_bar = Omega_m rho_crit, rho_crit = 3 H0^2 / (8 pi G))
   double radial() const { return newtonian_test ? 0.0 : 0.5 * omega_m * h0 * h0; }

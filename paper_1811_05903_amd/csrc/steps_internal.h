@@ -133,6 +133,12 @@ hipError_t launch_reduce_partials1(const double *part, int jsplit, int n,
 
 // Energy sums out[6] = (sum 1/2 m|v|^2, sum 1/2 m phi, sum m|x|^2,
 // sum m v_x, sum m v_y, sum m v_z); part holds energy_blocks(n) * 6 doubles.
+// adaptive step: out[0] <- min_i 2.8 h_i / |g S_i + rad x_i - drag v_i|
+int dt_blocks(int n);
+hipError_t launch_dt_min(const double *pos, const double *vel,
+                         const double *acc, const double *soft, int n,
+                         double g, double rad, double drag, double *part,
+                         double *out, hipStream_t s);
 int energy_blocks(int n);
 hipError_t launch_energy(const double *pos, const double *vel,
                          const double *mass, const double *phi, int n,

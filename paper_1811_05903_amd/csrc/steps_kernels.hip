@@ -226,7 +226,64 @@ __global__ __launch_bounds__(kBlock) void k_energy_final(
   }
 }
 
+// Adaptive step (Eq. 12): per block the smallest 2.8 h_i / |A_i| over its
+// particles, A_i = g S_i + rad x_i - drag v_i (the kick's acceleration at
+// the start of the step); +inf where A_i = 0.  min is exact, so the result
+// does not depend on the order.
+__global__ __launch_bounds__(kBlock) void k_dt_partial(
+    const double *__restrict__ pos, const double *__restrict__ vel,
+    const double *__restrict__ acc, const double *__restrict__ soft, int n,
+    double g, double rad, double drag, double *__restrict__ part) {
+  __shared__ double red[kBlock];
+  double q = INFINITY;
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += gridDim.x * kBlock) {
+    double a2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const size_t k = (size_t)d * n + i;
+      const double ad = g * acc[k] + rad * pos[k] - drag * vel[k];
+      a2 = fma(ad, ad, a2);
+    }
+    if (a2 > 0.0) q = fmin(q, 2.8 * soft[i] / sqrt(a2));
+  }
+  red[threadIdx.x] = q;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_dt_final(
+    const double *__restrict__ part, int nb, double *__restrict__ out) {
+  __shared__ double red[kBlock];
+  double q = INFINITY;
+  for (int b = threadIdx.x; b < nb; b += kBlock) q = fmin(q, part[b]);
+  red[threadIdx.x] = q;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
 }  // namespace
+
+int dt_blocks(int n) { return std::max(1, std::min(512, ceil_div(n, kBlock))); }
+
+hipError_t launch_dt_min(const double *pos, const double *vel,
+                         const double *acc, const double *soft, int n,
+                         double g, double rad, double drag, double *part,
+                         double *out, hipStream_t s) {
+  const int nb = dt_blocks(n);
+  hipLaunchKernelGGL(k_dt_partial, dim3(nb), dim3(kBlock), 0, s, pos, vel, acc,
+                     soft, n, g, rad, drag, part);
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(kBlock), 0, s, part, nb, out);
+  return hipGetLastError();
+}
 
 int energy_blocks(int n) { return std::max(1, std::min(512, ceil_div(n, kBlock))); }
 
