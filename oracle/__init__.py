@@ -91,7 +91,7 @@ class _Cosmo(ctypes.Structure):
     _fields_ = [("H0", ctypes.c_double), ("omega_m", ctypes.c_double),
                 ("omega_l", ctypes.c_double), ("omega_r", ctypes.c_double),
                 ("omega_k", ctypes.c_double), ("G", ctypes.c_double),
-                ("newtonian_test", ctypes.c_int)]
+                ("newtonian_test", ctypes.c_int), ("reversed_gravity", ctypes.c_int)]
 
 
 @dataclass
@@ -106,6 +106,7 @@ class Cosmology:
     omega_k: float | None = None
     G: float | None = None
     newtonian_test: bool = False
+    reversed_gravity: bool = False   # G -> -G (glass relaxation, Sec. 3)
 
     def _c(self) -> _Cosmo:
         ok = self.omega_k
@@ -113,7 +114,8 @@ class Cosmology:
             ok = 1.0 - self.omega_m - self.omega_l - self.omega_r
         g = G() if self.G is None else self.G
         return _Cosmo(self.H0, self.omega_m, self.omega_l, self.omega_r, ok,
-                      g, 1 if self.newtonian_test else 0)
+                      g, 1 if self.newtonian_test else 0,
+                      1 if self.reversed_gravity else 0)
 
 
 def G() -> float:

@@ -51,6 +51,9 @@
  *     it Plummer-equivalent although the spline's phi(0) = -2.8/h would make
  *     that h/2.8; the printed factor is kept) and |A_i| the magnitude of the
  *     kick's acceleration of Eq. 8 at the start of the step.
+ *   - Reversed gravity, for the glass relaxation of Sec. 3, flips the sign
+ *     of G in both the pair term and the radial term of Eq. 8 (the latter
+ *     is the gravity of the matter outside); the drag is unchanged.
  *
  * Units: Mpc, Gyr, solar masses.  H0 is given in km/s/Mpc.
  */
@@ -231,7 +234,16 @@ typedef struct {
   double omega_k; /* given explicitly */
   double G;       /* Mpc^3 / (Msun Gyr^2) */
   int newtonian_test; /* 1: a == 1, H == 0, no radial term, dt = da */
+  int reversed_gravity; /* 1: G -> -G in the pair and the radial term */
 } oracle_cosmo;
+
+/* G and the radial coefficient Omega_m H0^2 / 2 as the equations of motion
+ * use them: both change sign under reversed gravity (the glass relaxation of
+ * Sec. 3 integrates Eq. 8 with gravity reversed; the radial term stands for
+ * the gravity of the matter outside, so it is reversed with it). */
+static double oracle_G_eff(const oracle_cosmo *c) {
+  return c->reversed_gravity ? -c->G : c->G;
+}
 
 /* Hubble rate H(a) in 1/Gyr from the first Friedmann equation (Eq. 1). */
 double oracle_hubble(double a, const oracle_cosmo *c) {
@@ -294,12 +306,13 @@ double oracle_dt(double a, double da, const oracle_cosmo *c) {
 static void oracle_kick(int64_t n, const double *pos, double *vel,
                         const double *S, double a, double dt,
                         const oracle_cosmo *c, int end) {
-  double G = c->G;
+  double G = oracle_G_eff(c);
   double ainv3 = 1.0, radial = 0.0, drag = 0.0;
   if (!c->newtonian_test) {
     double h0 = c->H0 * oracle_kms_to_mpc_per_gyr();
     ainv3 = 1.0 / (a * a * a);
     radial = 0.5 * c->omega_m * h0 * h0;
+    if (c->reversed_gravity) radial = -radial;
     drag = 2.0 * oracle_hubble(a, c);
   }
   for (int d = 0; d < 3; ++d) {
@@ -373,14 +386,16 @@ int oracle_adaptive_dt(int64_t n, const double *pos, const double *vel,
     double h0 = c->H0 * oracle_kms_to_mpc_per_gyr();
     ainv3 = 1.0 / (a * a * a);
     radial = 0.5 * c->omega_m * h0 * h0;
+    if (c->reversed_gravity) radial = -radial;
     drag = 2.0 * oracle_hubble(a, c);
   }
+  double G = oracle_G_eff(c);
   double dt = dt_max;
   for (int64_t i = 0; i < n; ++i) {
     double A2 = 0.0;
     for (int d = 0; d < 3; ++d) {
       double x = pos[d * n + i], v = vel[d * n + i], s = S[d * n + i];
-      double Ad = c->G * s * ainv3 + radial * x * ainv3 - drag * v;
+      double Ad = G * s * ainv3 + radial * x * ainv3 - drag * v;
       A2 += Ad * Ad;
     }
     if (A2 > 0.0) {
@@ -443,13 +458,15 @@ int oracle_energy(int64_t n, const double *pos, const double *vel,
   }
   double h0 = c->H0 * oracle_kms_to_mpc_per_gyr();
   double rad = c->newtonian_test ? 0.0 : 0.25 * c->omega_m * h0 * h0;
+  double G = oracle_G_eff(c);
+  if (c->reversed_gravity) rad = -rad;
   nsum kin = {0, 0}, upair = {0, 0}, urad = {0, 0};
   nsum px = {0, 0}, py = {0, 0}, pz = {0, 0};
   for (int64_t i = 0; i < n; ++i) {
     double vx = vel[i], vy = vel[n + i], vz = vel[2 * n + i];
     double x = pos[i], y = pos[n + i], z = pos[2 * n + i];
     nsum_add(&kin, 0.5 * mass[i] * a * a * (vx * vx + vy * vy + vz * vz));
-    nsum_add(&upair, 0.5 * c->G * mass[i] * phi[i]);
+    nsum_add(&upair, 0.5 * G * mass[i] * phi[i]);
     nsum_add(&urad, -rad * mass[i] * (x * x + y * y + z * z));
     nsum_add(&px, mass[i] * a * a * vx);
     nsum_add(&py, mass[i] * a * a * vy);

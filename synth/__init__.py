@@ -190,6 +190,26 @@ def config(k: int, n: int | None = None, member: int = 0) -> ParticleSet:
     raise ValueError("no single-set workload %r" % (k,))
 
 
+def poisson_ball(n: int, radius: float, cosmo: Cosmo, seed: int,
+                 a0: float = 0.01, a1: float = 1.0, nsteps: int = 150,
+                 soft_frac: float = 0.05) -> ParticleSet:
+    """Equal-mass Poisson points in a ball of the given comoving radius at
+    the mean matter density (the starting load of a glass relaxation), at
+    rest; softening soft_frac times the mean spacing."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = rng.standard_normal((3, n))
+    g /= np.linalg.norm(g, axis=0)
+    pos = np.ascontiguousarray(g * radius * rng.uniform(size=n) ** (1.0 / 3.0))
+    h0 = cosmo.H0 * KMS_TO_MPC_PER_GYR
+    rho_bar = cosmo.omega_m * 3.0 * h0 * h0 / (8.0 * math.pi * G_MPC3_MSUN_GYR2)
+    m = rho_bar * 4.0 * math.pi / 3.0 * radius ** 3 / n
+    spacing = (m / rho_bar) ** (1.0 / 3.0)
+    return ParticleSet(pos=pos, vel=np.zeros_like(pos), mass=np.full(n, m),
+                       soft=np.full(n, soft_frac * spacing), cosmo=cosmo,
+                       a0=a0, a1=a1, nsteps=nsteps, seed=seed,
+                       params={"radius": radius, "spacing": spacing})
+
+
 def ensemble_params(members: int = 64, seed: int = 4999):
     """Per-member parameters of workload 4: N ~ U{8192..131072},
     Omega_m ~ U[0.25, 0.35] (flat, H0=70), sigma ~ U[0.5%, 2%]."""
