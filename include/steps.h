@@ -81,6 +81,13 @@ extern "C" {
 /* Plain Newtonian test mode: a == 1, H == 0, no radial term, the step
  * variable is time itself (dt = da).  For integrator tests only. */
 #define STEPS_NEWTONIAN_TEST 1
+/* steps_cosmology.flags: reversed gravity, G -> -G in both the pair term
+ * and the mean-density (radial) term of Eq. 8, the Hubble drag unchanged.
+ * Integrating with it relaxes a particle set into a glass, the way the
+ * paper prepares its initial particle loads (Sec. 3): the particles repel
+ * each other, the reversed radial term holds the sphere together, the drag
+ * damps the motion.  Energies follow the reversed potential. */
+#define STEPS_REVERSED_GRAVITY 1
 
 /* Background cosmology (Sec. 2.2 Eq. 1). */
 typedef struct steps_cosmology {
@@ -91,7 +98,7 @@ typedef struct steps_cosmology {
   double omega_k; /* curvature; NaN means 1 - omega_m - omega_l - omega_r */
   double G;       /* Newton's constant in Mpc^3/(Msun Gyr^2); 0 = built-in */
   int32_t mode;   /* STEPS_COMOVING_SPHERICAL or STEPS_NEWTONIAN_TEST */
-  int32_t reserved; /* must be 0 */
+  int32_t flags;  /* 0 or STEPS_REVERSED_GRAVITY */
 } steps_cosmology;
 
 /* Launch shape of the force kernels.  r: i-particles held per lane;

@@ -46,6 +46,7 @@ STEPS_PROFILE = 2
 
 STEPS_COMOVING_SPHERICAL = 0
 STEPS_NEWTONIAN_TEST = 1
+STEPS_REVERSED_GRAVITY = 1
 
 # every symbol include/steps.h declares
 EXPORTS = (
@@ -76,7 +77,7 @@ class steps_cosmology(ctypes.Structure):
     _fields_ = [("H0", ctypes.c_double), ("omega_m", ctypes.c_double),
                 ("omega_l", ctypes.c_double), ("omega_r", ctypes.c_double),
                 ("omega_k", ctypes.c_double), ("G", ctypes.c_double),
-                ("mode", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class steps_batch(ctypes.Structure):
@@ -107,13 +108,15 @@ class Cosmology:
     omega_k: float | None = None
     G: float = 0.0
     newtonian_test: bool = False
+    reversed_gravity: bool = False
 
     def to_c(self) -> steps_cosmology:
         ok = math.nan if self.omega_k is None else float(self.omega_k)
         mode = STEPS_NEWTONIAN_TEST if self.newtonian_test else STEPS_COMOVING_SPHERICAL
+        flags = STEPS_REVERSED_GRAVITY if self.reversed_gravity else 0
         return steps_cosmology(float(self.H0), float(self.omega_m),
                                float(self.omega_l), float(self.omega_r), ok,
-                               float(self.G), mode, 0)
+                               float(self.G), mode, flags)
 
 
 _lib = None

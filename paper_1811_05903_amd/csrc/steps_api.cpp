@@ -451,7 +451,9 @@ steps_ctx *default_ctx(int *rc) {
 
 int validate_cosmo(const steps_cosmology *k) {
   if (!k) return fail(STEPS_E_INVAL, "cosmology is NULL");
-  if (k->reserved != 0) return fail(STEPS_E_INVAL, "cosmology.reserved != 0");
+  if (k->flags & ~STEPS_REVERSED_GRAVITY) {
+    return fail(STEPS_E_INVAL, "unknown cosmology flag bits 0x%x", k->flags);
+  }
   if (k->mode != STEPS_COMOVING_SPHERICAL && k->mode != STEPS_NEWTONIAN_TEST) {
     return fail(STEPS_E_INVAL, "unknown cosmology mode %d", k->mode);
   }
@@ -476,7 +478,8 @@ steps::Background make_background(const steps_cosmology *k) {
                         ? 1.0 - k->omega_m - k->omega_l - k->omega_r
                         : k->omega_k;
   return steps::Background(k->H0, k->omega_m, k->omega_l, k->omega_r, ok,
-                           k->G, k->mode == STEPS_NEWTONIAN_TEST);
+                           k->G, k->mode == STEPS_NEWTONIAN_TEST,
+                           (k->flags & STEPS_REVERSED_GRAVITY) != 0);
 }
 
 int check_force_args(steps_ctx *c, const double *pos, const double *mass,

@@ -417,7 +417,9 @@ __device__ __forceinline__ void force_block_f64_mfma(
       }
       const int arow = 4 * (l & 3) + kk;  // gram[4 (4g + (l & 3)) + k]
       const int brow = 4 * kk + cc;       // bmat[4 (4g + k) + c]
-#pragma unroll 2
+      // not unrolled: measured 2% faster than unrolling by 2 (the four
+      // independent r chains already give the scheduler enough to interleave)
+#pragma unroll 1
       for (int g = 0; g < TJ / 4; ++g) {
         const double a1 = gram[16 * g + arow];
         const double b2 = bmat[16 * g + brow];

@@ -97,15 +97,22 @@ def test_negative_h2_rejected(lib):
         st.steps_dt(st.Cosmology(70.0, 0.3, 0.7), 0.1, -0.2)   # a + da <= 0
 
 
-def test_bad_mode_and_reserved(lib):
+def test_bad_mode_and_flags(lib):
     k = st.Cosmology().to_c()
     k.mode = 7
     out = ctypes.c_double()
     assert lib.steps_dt(ctypes.byref(k), 0.1, 0.1, ctypes.byref(out)) == st.STEPS_E_INVAL
     k = st.Cosmology().to_c()
-    k.reserved = 1
+    k.flags = 2
     assert lib.steps_dt(ctypes.byref(k), 0.1, 0.1, ctypes.byref(out)) == st.STEPS_E_INVAL
-    assert b"reserved" in lib.steps_last_error()
+    assert b"flag" in lib.steps_last_error()
+    # reversed gravity leaves the background (H, dt) as it is
+    ref = ctypes.c_double()
+    k = st.Cosmology().to_c()
+    assert lib.steps_dt(ctypes.byref(k), 0.1, 0.1, ctypes.byref(ref)) == st.STEPS_OK
+    k.flags = st.STEPS_REVERSED_GRAVITY
+    assert lib.steps_dt(ctypes.byref(k), 0.1, 0.1, ctypes.byref(out)) == st.STEPS_OK
+    assert out.value == ref.value
 
 
 def test_null_arguments_rejected_before_device_use(lib):
