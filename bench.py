@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 5])
+    ap.add_argument("--no-glass", action="store_true",
+                    help="skip the glass-relaxation leg")
     ap.add_argument("--li-study-only", action="store_true",
                     help="workload 5: only the Layzer-Irvine step-convergence "
                          "study at N = 2^17")
@@ -199,6 +201,8 @@ def main():
         out["modes_n2e21"] = mode_table(st, big, big_rows, dev)
     if not args.no_batch:
         out["batch"] = batch_leg(st, dev, args.batch_steps)
+    if not args.no_glass:
+        out["glass"] = glass_leg(st, dev)
     ctx.close()
     if args.copy_calibration:
         nb = args.copy_calibration << 20
@@ -426,6 +430,44 @@ def workload5(st, dev, args):
         "at a=1: mixed %.2e fp64 %.2e"
         % (res["mixed"]["pairs_per_s"], res["fp64"]["pairs_per_s"],
            res["mixed"]["layzer_irvine"][-1]["rel"], res["fp64"]["layzer_irvine"][-1]["rel"]))
+    return out
+
+
+def glass_leg(st, dev, n=262144, radius=500.0):
+    """Glass relaxation (Sec. 3): an equal-mass Poisson ball of N = 2^18 at
+    the mean density, 150 log steps a 0.01 -> 1 with reversed gravity, FP64;
+    the nearest-neighbour distance spread (std/mean, inner 80% of the
+    radius) before and after."""
+    import numpy as np
+    import torch
+    import synth
+    from scipy.spatial import cKDTree
+    ps = synth.poisson_ball(n, radius, synth.Cosmo(67.74, 0.3089, 0.6911), seed=31)
+
+    def cv(pos):
+        d, _ = cKDTree(pos.T).query(pos.T, k=2)
+        keep = np.linalg.norm(pos, axis=0) < 0.8 * radius
+        return float(d[keep, 1].std() / d[keep, 1].mean())
+
+    c = ps.cosmo
+    cosmo = st.Cosmology(c.H0, c.omega_m, c.omega_l, c.omega_r, reversed_gravity=True)
+    grid = ps.a_grid()
+    p, v, m, h = dev(ps.pos), dev(ps.vel), dev(ps.mass), dev(ps.soft)
+    ctx = st.Context(0, precision="fp64")
+    acc = st.steps_forces(p, m, h, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(len(grid) - 1):
+        st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], cosmo, ctx=ctx)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.close()
+    out = {"n": n, "steps": len(grid) - 1, "seconds": elapsed,
+           "pairs_per_s": float(n) * n * (len(grid) - 1) / elapsed,
+           "nn_cv_start": cv(ps.pos), "nn_cv_glass": cv(p.cpu().numpy())}
+    log("glass: N=%d, %d steps in %.1f s (%.3e pairs/s); nearest-neighbour "
+        "spread %.3f -> %.3f" % (n, out["steps"], elapsed, out["pairs_per_s"],
+                                  out["nn_cv_start"], out["nn_cv_glass"]))
     return out
 
 
