@@ -77,6 +77,9 @@ def _load():
                                            ctypes.POINTER(_Cosmo), d, d,
                                            ctypes.POINTER(d), ctypes.POINTER(d)]
         lib.oracle_adaptive_dt.restype = i32
+        lib.oracle_forces_periodic.argtypes = [i64, vp, vp, vp, d, i32, i64,
+                                               vp, vp, i32]
+        lib.oracle_forces_periodic.restype = i32
         lib.oracle_G.argtypes = []
         lib.oracle_G.restype = d
         lib.oracle_kms_to_mpc_per_gyr.argtypes = []
@@ -91,7 +94,8 @@ class _Cosmo(ctypes.Structure):
     _fields_ = [("H0", ctypes.c_double), ("omega_m", ctypes.c_double),
                 ("omega_l", ctypes.c_double), ("omega_r", ctypes.c_double),
                 ("omega_k", ctypes.c_double), ("G", ctypes.c_double),
-                ("newtonian_test", ctypes.c_int), ("reversed_gravity", ctypes.c_int)]
+                ("newtonian_test", ctypes.c_int), ("reversed_gravity", ctypes.c_int),
+                ("images", ctypes.c_int), ("box_L", ctypes.c_double)]
 
 
 @dataclass
@@ -107,6 +111,8 @@ class Cosmology:
     G: float | None = None
     newtonian_test: bool = False
     reversed_gravity: bool = False   # G -> -G (glass relaxation, Sec. 3)
+    images: int = 0      # 0 open sphere; 1 nearest image, 2 all within 2.6 L
+    box_L: float = 0.0   # periodic box side (Eq. 2), used when images > 0
 
     def _c(self) -> _Cosmo:
         ok = self.omega_k
@@ -115,7 +121,8 @@ class Cosmology:
         g = G() if self.G is None else self.G
         return _Cosmo(self.H0, self.omega_m, self.omega_l, self.omega_r, ok,
                       g, 1 if self.newtonian_test else 0,
-                      1 if self.reversed_gravity else 0)
+                      1 if self.reversed_gravity else 0, int(self.images),
+                      float(self.box_L))
 
 
 def G() -> float:
@@ -264,6 +271,34 @@ def layzer_irvine(energies, a_grid, cosmo: Cosmology):
     return np.array(out)
 
 
+def _initial_S(pos, mass, soft, cosmo: Cosmology, nthreads=0):
+    if cosmo.images:
+        return forces_periodic(pos, mass, soft, cosmo.box_L, cosmo.images,
+                               nthreads=nthreads)
+    return forces(pos, mass, soft, nthreads=nthreads)
+
+
+def forces_periodic(pos, mass, soft, L, images, idx=None, nthreads=0):
+    """G-free periodic pair sum (Eqs. 2 and 5; see oracle.c): images 1 keeps
+    the nearest image, 2 every image within 2.6 L.  (3, ni) array."""
+    mass = np.ascontiguousarray(mass, dtype=np.float64)
+    n = mass.shape[0]
+    pos = _soa(pos, n)
+    soft = np.ascontiguousarray(soft, dtype=np.float64)
+    if idx is None:
+        ni, ip = n, None
+    else:
+        idx = np.ascontiguousarray(idx, dtype=np.int64)
+        ni, ip = idx.shape[0], _ptr(idx)
+    acc = np.zeros((3, ni), dtype=np.float64)
+    rc = _load().oracle_forces_periodic(n, _ptr(pos), _ptr(mass), _ptr(soft),
+                                        float(L), int(images), ni, ip,
+                                        _ptr(acc), int(nthreads))
+    if rc:
+        raise ValueError("oracle_forces_periodic: bad argument")
+    return acc
+
+
 def adaptive_dt(pos, vel, soft, S, a, cosmo: Cosmology, eps, dt_max):
     """Global step of Eq. 12 at the current state (see oracle.c): returns
     (dt, da), da being the scale-factor step whose cosmic time is dt."""
@@ -290,7 +325,7 @@ def run_adaptive(pos, vel, mass, soft, a0, a1, cosmo: Cosmology, eps, dt_max,
     n = mass.shape[0]
     pos = _soa(pos, n).copy()
     vel = _soa(vel, n).copy()
-    S = forces(pos, mass, soft, nthreads=nthreads)
+    S = _initial_S(pos, mass, soft, cosmo, nthreads)
     a, grid = float(a0), [float(a0)]
     for _ in range(max_steps):
         if a >= a1:
@@ -313,7 +348,7 @@ def run(pos, vel, mass, soft, a_grid, cosmo: Cosmology, nthreads=0):
     n = mass.shape[0]
     pos = _soa(pos, n).copy()
     vel = _soa(vel, n).copy()
-    S = forces(pos, mass, soft, nthreads=nthreads)
+    S = _initial_S(pos, mass, soft, cosmo, nthreads)
     for k in range(len(a_grid) - 1):
         kdk_step(pos, vel, mass, soft, S, a_grid[k],
                  a_grid[k + 1] - a_grid[k], cosmo, nthreads)

@@ -54,6 +54,12 @@
  *   - Reversed gravity, for the glass relaxation of Sec. 3, flips the sign
  *     of G in both the pair term and the radial term of Eq. 8 (the latter
  *     is the gravity of the matter outside); the drag is unchanged.
+ *   - Periodic boxes (Eqs. 2 and 5): the paper names Ewald summation, but
+ *     the formula it prints -- and this oracle -- is the direct sum over
+ *     the images within 2.6 L, with no Fourier-space part.  A particle's
+ *     own images cancel in pairs and are left out; the quasi-periodic
+ *     option keeps the nearest image, ties broken to even.  Eq. 2 has no
+ *     radial term.
  *
  * Units: Mpc, Gyr, solar masses.  H0 is given in km/s/Mpc.
  */
@@ -224,6 +230,71 @@ int oracle_potential(int64_t n, const double *pos, const double *mass,
   return 0;
 }
 
+/* ---- periodic pair sum, Sec. 2.2 Eqs. 2 and 5 ------------------------- */
+
+/*
+ * Periodic box of side L: the pair term of Eq. 2 with the force of Eq. 5,
+ * which sums the softened force over the images x_j + n L of every other
+ * particle.
+ *   images = 2: every integer triplet n with |x_j + n L - x_i| < 2.6 L (the
+ *               cut the paper uses);
+ *   images = 1: the leading term only -- the nearest image (the
+ *               quasi-periodic option).
+ * The nearest image of d = x_j - x_i is d - L nearbyint(d / L) per component
+ * (ties to even: a pair exactly L/2 apart along an axis has two nearest
+ * images, and this picks one).  The image sum starts from it and tests every
+ * n in [-3, 3]^3, which holds every image within 2.6 L of a nearest-image
+ * displacement (each |d_k| <= L/2).  Particle i's own images cancel in
+ * pairs (n and -n) and are left out.  G-free, like oracle_forces.
+ * Returns 0, or -1 on a bad argument.
+ */
+int oracle_forces_periodic(int64_t n, const double *pos, const double *mass,
+                           const double *soft, double L, int images,
+                           int64_t ni, const int64_t *idx, double *acc,
+                           int nthreads) {
+  if (n < 0 || ni < 0 || (n > 0 && (!pos || !mass || !soft)) ||
+      (ni > 0 && !acc) || (!idx && ni != n) || !(L > 0.0) ||
+      (images != 1 && images != 2)) {
+    return -1;
+  }
+  const double *X = pos, *Y = pos + n, *Z = pos + 2 * n;
+  const double cut2 = (2.6 * L) * (2.6 * L);
+#ifdef _OPENMP
+  if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+#endif
+  for (int64_t k = 0; k < ni; ++k) {
+    int64_t i = idx ? idx[k] : k;
+    nsum sx = {0, 0}, sy = {0, 0}, sz = {0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      double d[3] = {X[j] - X[i], Y[j] - Y[i], Z[j] - Z[i]};
+      for (int c = 0; c < 3; ++c) d[c] -= L * nearbyint(d[c] / L);
+      double h = soft[i] + soft[j];
+      int lim = images == 1 ? 0 : 3;
+      for (int a = -lim; a <= lim; ++a) {
+        for (int b = -lim; b <= lim; ++b) {
+          for (int e = -lim; e <= lim; ++e) {
+            double ex = d[0] + a * L, ey = d[1] + b * L, ez = d[2] + e * L;
+            double r2 = ex * ex + ey * ey + ez * ez;
+            if (images == 2 && !(r2 < cut2)) continue;
+            double r = sqrt(r2);
+            if (r == 0.0) continue;
+            double f = mass[j] * oracle_kernel_F(r, h) / r;
+            nsum_add(&sx, f * ex);
+            nsum_add(&sy, f * ey);
+            nsum_add(&sz, f * ez);
+          }
+        }
+      }
+    }
+    acc[k] = nsum_get(&sx);
+    acc[ni + k] = nsum_get(&sy);
+    acc[2 * ni + k] = nsum_get(&sz);
+  }
+  return 0;
+}
+
 /* ---- background cosmology, Sec. 2.2 Eq. 1 and Sec. 2.3 Eq. 13 -------- */
 
 typedef struct {
@@ -235,6 +306,10 @@ typedef struct {
   double G;       /* Mpc^3 / (Msun Gyr^2) */
   int newtonian_test; /* 1: a == 1, H == 0, no radial term, dt = da */
   int reversed_gravity; /* 1: G -> -G in the pair and the radial term */
+  int images;           /* 0: open sphere (Eq. 8); 1, 2: periodic box of
+                           side box_L (Eq. 2) with the image rule of
+                           oracle_forces_periodic, and no radial term */
+  double box_L;
 } oracle_cosmo;
 
 /* G and the radial coefficient Omega_m H0^2 / 2 as the equations of motion
@@ -311,7 +386,7 @@ static void oracle_kick(int64_t n, const double *pos, double *vel,
   if (!c->newtonian_test) {
     double h0 = c->H0 * oracle_kms_to_mpc_per_gyr();
     ainv3 = 1.0 / (a * a * a);
-    radial = 0.5 * c->omega_m * h0 * h0;
+    radial = c->images ? 0.0 : 0.5 * c->omega_m * h0 * h0;
     if (c->reversed_gravity) radial = -radial;
     drag = 2.0 * oracle_hubble(a, c);
   }
@@ -352,7 +427,10 @@ int oracle_kdk_step(int64_t n, double *pos, double *vel, const double *mass,
   double dt = oracle_dt(a, da, c);
   oracle_kick(n, pos, vel, S, a, 0.5 * dt, c, 0);
   oracle_drift(n, pos, vel, dt);
-  int rc = oracle_forces(n, pos, mass, soft, n, NULL, S, NULL, nthreads);
+  int rc = c->images
+               ? oracle_forces_periodic(n, pos, mass, soft, c->box_L,
+                                        c->images, n, NULL, S, nthreads)
+               : oracle_forces(n, pos, mass, soft, n, NULL, S, NULL, nthreads);
   if (rc) return rc;
   oracle_kick(n, pos, vel, S, a + da, 0.5 * dt, c, 1);
   return 0;
@@ -385,7 +463,7 @@ int oracle_adaptive_dt(int64_t n, const double *pos, const double *vel,
   if (!c->newtonian_test) {
     double h0 = c->H0 * oracle_kms_to_mpc_per_gyr();
     ainv3 = 1.0 / (a * a * a);
-    radial = 0.5 * c->omega_m * h0 * h0;
+    radial = c->images ? 0.0 : 0.5 * c->omega_m * h0 * h0;
     if (c->reversed_gravity) radial = -radial;
     drag = 2.0 * oracle_hubble(a, c);
   }
