@@ -81,6 +81,11 @@ extern "C" {
 /* Plain Newtonian test mode: a == 1, H == 0, no radial term, the step
  * variable is time itself (dt = da).  For integrator tests only. */
 #define STEPS_NEWTONIAN_TEST 1
+/* Comoving equations of motion in a periodic box, Sec. 2.2 Eq. 2: the pair
+ * term and the Hubble drag, no radial term.  Needs a context made periodic
+ * with steps_ctx_set_periodic (and the spherical mode needs one that is
+ * not). */
+#define STEPS_COMOVING_PERIODIC 2
 /* steps_cosmology.flags: reversed gravity, G -> -G in both the pair term
  * and the mean-density (radial) term of Eq. 8, the Hubble drag unchanged.
  * Integrating with it relaxes a particle set into a glass, the way the
@@ -97,7 +102,8 @@ typedef struct steps_cosmology {
   double omega_r; /* radiation density parameter */
   double omega_k; /* curvature; NaN means 1 - omega_m - omega_l - omega_r */
   double G;       /* Newton's constant in Mpc^3/(Msun Gyr^2); 0 = built-in */
-  int32_t mode;   /* STEPS_COMOVING_SPHERICAL or STEPS_NEWTONIAN_TEST */
+  int32_t mode;   /* STEPS_COMOVING_SPHERICAL, STEPS_NEWTONIAN_TEST or
+                     STEPS_COMOVING_PERIODIC */
   int32_t flags;  /* 0 or STEPS_REVERSED_GRAVITY */
 } steps_cosmology;
 
@@ -138,6 +144,26 @@ int steps_ctx_set_flags(steps_ctx *ctx, uint32_t flags);
  * must name one of them, jsplit >= 1).  Passing NULL returns to automatic
  * selection (tuned table, else heuristic). */
 int steps_ctx_set_tile(steps_ctx *ctx, const steps_tile *tile);
+/* Periodic box (Sec. 2.2, Eqs. 2 and 5).  With images != NONE every pair
+ * sum on this context (steps_forces_ctx, steps_step_ctx, the adaptive step)
+ * is taken in a box of side L:
+ *   STEPS_IMAGES_ALL:     the softened force summed over every image x_j + n L
+ *                         with |x_j + n L - x_i| < 2.6 L -- the formula of
+ *                         Eq. 5 as printed, a direct image sum with no
+ *                         Fourier-space part;
+ *   STEPS_IMAGES_NEAREST: the leading term only, the nearest image (the
+ *                         quasi-periodic option; ties at exactly L/2 go to
+ *                         the even image);
+ *   STEPS_IMAGES_NONE:    back to the open sphere (the default).
+ * A particle's own images cancel in pairs and are left out.  Positions may
+ * lie anywhere (the sums depend on them modulo L) and are not wrapped.
+ * FP64 only (STEPS_E_UNSUPPORTED in the mixed modes); no potential, energy,
+ * autotune or ensemble (STEPS_E_UNSUPPORTED).  The full image sum costs
+ * about 180 image tests and 74 pair terms per pair.  L finite and > 0. */
+#define STEPS_IMAGES_NONE 0
+#define STEPS_IMAGES_NEAREST 1
+#define STEPS_IMAGES_ALL 2
+int steps_ctx_set_periodic(steps_ctx *ctx, double L, int32_t images);
 /* Record `tile` as the tuned shape for n particles in the context's current
  * precision, as steps_autotune would (validated like steps_ctx_set_tile;
  * replaces an earlier entry for the same precision and n).  For restoring a

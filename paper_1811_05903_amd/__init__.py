@@ -47,12 +47,15 @@ STEPS_PROFILE = 2
 STEPS_COMOVING_SPHERICAL = 0
 STEPS_NEWTONIAN_TEST = 1
 STEPS_REVERSED_GRAVITY = 1
+STEPS_COMOVING_PERIODIC = 2
+STEPS_IMAGES_NONE, STEPS_IMAGES_NEAREST, STEPS_IMAGES_ALL = 0, 1, 2
 
 # every symbol include/steps.h declares
 EXPORTS = (
     "steps_version", "steps_last_error", "steps_ctx_create",
     "steps_ctx_destroy", "steps_ctx_set_stream", "steps_ctx_set_precision",
     "steps_ctx_set_flags", "steps_ctx_set_tile", "steps_ctx_set_tuned",
+    "steps_ctx_set_periodic",
     "steps_ctx_get_tile",
     "steps_sync", "steps_ctx_force_timing", "steps_autotune", "steps_forces_ctx",
     "steps_forces", "steps_potential_ctx", "steps_potential",
@@ -109,10 +112,13 @@ class Cosmology:
     G: float = 0.0
     newtonian_test: bool = False
     reversed_gravity: bool = False
+    periodic: bool = False      # Eq. 2 (needs a periodic context)
 
     def to_c(self) -> steps_cosmology:
         ok = math.nan if self.omega_k is None else float(self.omega_k)
-        mode = STEPS_NEWTONIAN_TEST if self.newtonian_test else STEPS_COMOVING_SPHERICAL
+        mode = (STEPS_NEWTONIAN_TEST if self.newtonian_test else
+                STEPS_COMOVING_PERIODIC if self.periodic else
+                STEPS_COMOVING_SPHERICAL)
         flags = STEPS_REVERSED_GRAVITY if self.reversed_gravity else 0
         return steps_cosmology(float(self.H0), float(self.omega_m),
                                float(self.omega_l), float(self.omega_r), ok,
@@ -152,6 +158,7 @@ def load():
             "steps_ctx_set_tile": ([vp, pt], i32),
             "steps_ctx_get_tile": ([vp, i64, pt], i32),
             "steps_ctx_set_tuned": ([vp, i64, pt], i32),
+            "steps_ctx_set_periodic": ([vp, d, i32], i32),
             "steps_sync": ([vp], i32),
             "steps_ctx_force_timing": ([vp, ctypes.POINTER(d),
                                         ctypes.POINTER(i64), i32], i32),
@@ -275,6 +282,11 @@ class Context:
             return
         t = steps_tile(int(r), int(tj), int(jsplit), int(variant))
         _check(self._lib.steps_ctx_set_tile(self.handle, ctypes.byref(t)))
+
+    def set_periodic(self, L=0.0, images=STEPS_IMAGES_NONE):
+        """Periodic box of side L for this context's pair sums (images: 1
+        nearest image, 2 every image within 2.6 L, 0 open sphere)."""
+        _check(self._lib.steps_ctx_set_periodic(self.handle, float(L), int(images)))
 
     def set_tuned(self, n: int, r, tj, jsplit, variant=0):
         """Record a tuned shape for n in this precision (steps_ctx_set_tuned)."""

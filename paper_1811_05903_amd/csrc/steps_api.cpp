@@ -78,6 +78,9 @@ struct steps_ctx {
   Buffer arena;    // spatial-sort scratch (keys, permutation, sorted copy)
   Buffer diag;     // energy diagnostic: potential and reduction partials
   steps_tile batch_tile = {0, 0, 0, 0};  // shape of the last ensemble run
+  // periodic geometry (steps_ctx_set_periodic): images 0 = open sphere
+  double box_L = 0.0;
+  int images = STEPS_IMAGES_NONE;
   // shapes found by steps_autotune: (kernel class, n) -> tile
   std::vector<std::pair<std::pair<int, int64_t>, steps_tile>> tuned;
   int *flag = nullptr;  // device int for the finite check
@@ -271,9 +274,49 @@ struct Carve {
 };
 
 // Enqueue acc <- S(pos) in the context's precision.  Arguments validated.
+// Periodic pair sum: FP64 kernel over unsorted particles, j-split
+// partials reduced in fixed order.
+int run_forces_periodic(steps_ctx *c, const double *pos, const double *mass,
+                        const double *soft, int n, double *acc) {
+  if (c->precision != STEPS_FP64) {
+    return fail(STEPS_E_UNSUPPORTED,
+                "periodic boxes are computed in FP64 only");
+  }
+  const int tj = steps::periodic_tile();
+  const int64_t nb = steps::periodic_iblocks(n);
+  int64_t want = (8192 + nb - 1) / nb;
+  want = std::min<int64_t>(want, std::max<int64_t>(1, n / (2LL * tj)));
+  int chunk = 0, js = 1;
+  split_j(n, tj, (int)std::max<int64_t>(1, std::min<int64_t>(want, 1024)),
+          &chunk, &js);
+  double *out = acc;
+  int rc;
+  if (js > 1) {
+    rc = ensure(c, c->part, (size_t)js * 3 * (size_t)n * sizeof(double),
+                "partial-sum");
+    if (rc) return rc;
+    out = (double *)c->part.p;
+  }
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  if ((rc = prof_begin(c, ev))) return rc;
+  hipError_t e = steps::launch_force_periodic(pos, mass, soft, n, c->box_L,
+                                              c->images, chunk, js, out,
+                                              c->stream);
+  if (e != hipSuccess) return hip_fail(e, "periodic force kernel launch");
+  if ((rc = prof_end(c, ev))) return rc;
+  if (js > 1) {
+    e = steps::launch_reduce_partials(out, js, n, acc, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "partial reduction launch");
+  }
+  return STEPS_OK;
+}
+
 int run_forces(steps_ctx *c, const double *pos, const double *mass,
                const double *soft, int n, double *acc) {
   if (n == 0) return STEPS_OK;
+  if (c->images != STEPS_IMAGES_NONE) {
+    return run_forces_periodic(c, pos, mass, soft, n, acc);
+  }
   const int cls = prec_class(c->precision);
   const steps_tile t = choose_tile(c, n);
   const steps::ForceVariant *v =
@@ -454,13 +497,14 @@ int validate_cosmo(const steps_cosmology *k) {
   if (k->flags & ~STEPS_REVERSED_GRAVITY) {
     return fail(STEPS_E_INVAL, "unknown cosmology flag bits 0x%x", k->flags);
   }
-  if (k->mode != STEPS_COMOVING_SPHERICAL && k->mode != STEPS_NEWTONIAN_TEST) {
+  if (k->mode != STEPS_COMOVING_SPHERICAL && k->mode != STEPS_NEWTONIAN_TEST &&
+      k->mode != STEPS_COMOVING_PERIODIC) {
     return fail(STEPS_E_INVAL, "unknown cosmology mode %d", k->mode);
   }
   if (!std::isfinite(k->G) || k->G < 0.0) {
     return fail(STEPS_E_INVAL, "G must be finite and >= 0 (0 = built-in)");
   }
-  if (k->mode == STEPS_COMOVING_SPHERICAL) {
+  if (k->mode != STEPS_NEWTONIAN_TEST) {
     if (!std::isfinite(k->H0) || k->H0 <= 0.0) {
       return fail(STEPS_E_INVAL, "H0 must be finite and > 0");
     }
@@ -479,7 +523,8 @@ steps::Background make_background(const steps_cosmology *k) {
                         : k->omega_k;
   return steps::Background(k->H0, k->omega_m, k->omega_l, k->omega_r, ok,
                            k->G, k->mode == STEPS_NEWTONIAN_TEST,
-                           (k->flags & STEPS_REVERSED_GRAVITY) != 0);
+                           (k->flags & STEPS_REVERSED_GRAVITY) != 0,
+                           k->mode == STEPS_COMOVING_PERIODIC);
 }
 
 int check_force_args(steps_ctx *c, const double *pos, const double *mass,
@@ -639,6 +684,25 @@ int steps_ctx_set_tuned(steps_ctx *c, int64_t n, const steps_tile *t) {
   return STEPS_OK;
 }
 
+int steps_ctx_set_periodic(steps_ctx *c, double L, int32_t images) {
+  if (!c) return fail(STEPS_E_INVAL, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(c->mu);
+  if (images == STEPS_IMAGES_NONE) {
+    c->images = STEPS_IMAGES_NONE;
+    c->box_L = 0.0;
+    return STEPS_OK;
+  }
+  if (images != STEPS_IMAGES_NEAREST && images != STEPS_IMAGES_ALL) {
+    return fail(STEPS_E_INVAL, "unknown image rule %d", images);
+  }
+  if (!std::isfinite(L) || !(L > 0.0)) {
+    return fail(STEPS_E_INVAL, "box side L must be finite and > 0");
+  }
+  c->images = images;
+  c->box_L = L;
+  return STEPS_OK;
+}
+
 int steps_ctx_get_tile(steps_ctx *c, int64_t n, steps_tile *out) {
   if (!c || !out) return fail(STEPS_E_INVAL, "ctx or out is NULL");
   int rc = check_n(n);
@@ -700,6 +764,9 @@ int steps_autotune(steps_ctx *c, const double *pos, const double *mass,
   if (!c || !out) return fail(STEPS_E_INVAL, "ctx or out is NULL");
   std::lock_guard<std::mutex> lk(c->mu);
   DeviceGuard g(c->device);
+  if (c->images != STEPS_IMAGES_NONE) {
+    return fail(STEPS_E_UNSUPPORTED, "the periodic kernel has one launch shape");
+  }
   int rc = check_force_args(c, pos, mass, soft, n, acc,
                             3 * (size_t)n * sizeof(double), "acc");
   if (rc) return rc;
@@ -796,6 +863,9 @@ int steps_potential_ctx(steps_ctx *c, const double *pos, const double *mass,
   int rc = check_force_args(c, pos, mass, soft, n, phi,
                             (size_t)n * sizeof(double), "phi");
   if (rc || n == 0) return rc;
+  if (c->images != STEPS_IMAGES_NONE) {
+    return fail(STEPS_E_UNSUPPORTED, "no softened potential for periodic boxes");
+  }
   if ((rc = check_finite(c, {{pos, 3 * n}, {mass, n}, {soft, n}}))) return rc;
   return run_potential(c, pos, mass, soft, (int)n, phi);
 }
@@ -809,6 +879,9 @@ int steps_energy_ctx(steps_ctx *c, const double *pos, const double *vel,
   DeviceGuard g(c->device);
   int rc = validate_cosmo(cosmo);
   if (rc) return rc;
+  if (c->images != STEPS_IMAGES_NONE || cosmo->mode == STEPS_COMOVING_PERIODIC) {
+    return fail(STEPS_E_UNSUPPORTED, "no energies for periodic boxes");
+  }
   const bool newton = cosmo->mode == STEPS_NEWTONIAN_TEST;
   if (newton) a = 1.0;
   if (!std::isfinite(a) || !(a > 0.0)) {
@@ -922,6 +995,15 @@ static int step_impl(steps_ctx *c, double *pos, double *vel, const double *mass,
                      double da, const steps_cosmology *cosmo) {
   int rc = validate_cosmo(cosmo);
   if (rc) return rc;
+  if (cosmo->mode == STEPS_COMOVING_PERIODIC && c->images == STEPS_IMAGES_NONE) {
+    return fail(STEPS_E_INVAL,
+                "periodic mode needs a periodic context (steps_ctx_set_periodic)");
+  }
+  if (cosmo->mode == STEPS_COMOVING_SPHERICAL && c->images != STEPS_IMAGES_NONE) {
+    return fail(STEPS_E_INVAL,
+                "the spherical equations of motion need an open (non-periodic) "
+                "context");
+  }
   if (!std::isfinite(a) || !std::isfinite(da)) {
     return fail(STEPS_E_INVAL, "a and da must be finite");
   }
@@ -1288,6 +1370,7 @@ hipError_t upload_layout(BatchRun &R, const BatchLayout &L) {
 int batch_member(const steps_cosmology *k, double a0, double a1, int nsteps,
                  int A, int a, std::vector<double> &table) {
   if (validate_cosmo(k) != STEPS_OK) return STEPS_E_INVAL;
+  if (k->mode == STEPS_COMOVING_PERIODIC) return STEPS_E_UNSUPPORTED;
   const bool newton = k->mode == STEPS_NEWTONIAN_TEST;
   // the log-uniform grid needs a0, a1 > 0 in both modes
   if (!std::isfinite(a0) || !std::isfinite(a1) || a0 <= 0.0 || a1 <= 0.0) {
@@ -1344,6 +1427,9 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
   if (!c || !b) return fail(STEPS_E_INVAL, "ctx or batch is NULL");
   std::lock_guard<std::mutex> lk(c->mu);
   DeviceGuard g(c->device);
+  if (c->images != STEPS_IMAGES_NONE) {
+    return fail(STEPS_E_UNSUPPORTED, "ensembles run the spherical equations only");
+  }
   const int B = b->members;
   if (B < 1) return fail(STEPS_E_INVAL, "members must be >= 1");
   if (b->nsteps < 1) return fail(STEPS_E_INVAL, "nsteps must be >= 1");

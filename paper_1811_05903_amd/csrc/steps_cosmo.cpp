@@ -40,11 +40,12 @@ double newton_G() {
 
 Background::Background(double H0_kms, double om, double ol, double orad,
                        double ok, double G, bool newtonian,
-                       bool reversed_gravity)
+                       bool reversed_gravity, bool periodic_box)
     : h0(H0_kms * kms_to_mpc_per_gyr()), omega_m(om), omega_l(ol),
       omega_r(orad), omega_k(ok),
       g((reversed_gravity ? -1.0 : 1.0) * (G > 0.0 ? G : newton_G())),
-      newtonian_test(newtonian), reversed(reversed_gravity) {}
+      newtonian_test(newtonian), reversed(reversed_gravity),
+      periodic(periodic_box) {}
 
 double Background::e2(double a) const {
   const double ia = 1.0 / a;

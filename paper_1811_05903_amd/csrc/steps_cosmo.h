@@ -12,9 +12,11 @@ struct Background {
   double g;   // Mpc^3 / (Msun Gyr^2), negative for reversed gravity
   bool newtonian_test;
   bool reversed;  // G -> -G in the pair and radial terms
+  bool periodic;  // periodic box (Eq. 2): no radial term
 
   Background(double H0_kms, double om, double ol, double orad, double ok,
-             double G, bool newtonian, bool reversed_gravity = false);
+             double G, bool newtonian, bool reversed_gravity = false,
+             bool periodic_box = false);
   // E(a)^2 = Omega_m a^-3 + Omega_r a^-4 + Omega_k a^-2 + Omega_Lambda
   double e2(double a) const;
   // H(a) in 1/Gyr (0 in the Newtonian test mode)
@@ -28,7 +30,9 @@ struct Background {
   // Eq. 8 with rho_bar = Omega_m rho_crit, rho_crit = 3 H0^2 / (8 pi G))
   // (negative for reversed gravity)
   double radial() const {
-    return newtonian_test ? 0.0 : (reversed ? -0.5 : 0.5) * omega_m * h0 * h0;
+    return newtonian_test || periodic
+               ? 0.0
+               : (reversed ? -0.5 : 0.5) * omega_m * h0 * h0;
   }
 };
 

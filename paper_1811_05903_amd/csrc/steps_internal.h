@@ -133,6 +133,14 @@ hipError_t launch_reduce_partials1(const double *part, int jsplit, int n,
 
 // Energy sums out[6] = (sum 1/2 m|v|^2, sum 1/2 m phi, sum m|x|^2,
 // sum m v_x, sum m v_y, sum m v_z); part holds energy_blocks(n) * 6 doubles.
+// periodic pair sum (Eqs. 2 and 5): images 1 = nearest image, 2 = every
+// image within 2.6 L; out as the force kernels ([jsplit][3][n] partials)
+int periodic_tile();
+int periodic_iblocks(int n);
+hipError_t launch_force_periodic(const double *pos, const double *mass,
+                                 const double *soft, int n, double L,
+                                 int images, int jchunk, int jsplit,
+                                 double *out, hipStream_t s);
 // adaptive step: out[0] <- min_i 2.8 h_i / |g S_i + rad x_i - drag v_i|
 int dt_blocks(int n);
 hipError_t launch_dt_min(const double *pos, const double *vel,
