@@ -201,6 +201,10 @@ def main():
         out["modes_n2e21"] = mode_table(st, big, big_rows, dev)
     if not args.no_batch:
         out["batch"] = batch_leg(st, dev, args.batch_steps)
+        # many small members (N_b ~ 256 ... 4096): where one launch per
+        # member and step would leave the GPU idle
+        out["batch_small"] = batch_leg(st, dev, args.batch_steps, members=256,
+                                       n_scale=1.0 / 32)
     if not args.no_glass:
         out["glass"] = glass_leg(st, dev)
         out["periodic"] = periodic_leg(st, dev)
@@ -499,15 +503,17 @@ def periodic_leg(st, dev):
     return out
 
 
-def batch_leg(st, dev, nsteps):
+def batch_leg(st, dev, nsteps, members=64, n_scale=1.0):
     """Workload 4: 64 members, N_b ~ U{8192..131072}, Omega_m ~ U[0.25,
     0.35] flat, 100 log steps a 0.02 -> 1.0, mixed precision: one
     steps_batch_run (persistent kernel, graph-replayed step, autotuned)
-    against the same members run one after another with steps_step."""
+    against the same members run one after another with steps_step.
+    members / n_scale give the many-small-runs variant (n_scale shrinks
+    every member's N)."""
     import numpy as np
     import torch
     import synth
-    members = synth.ensemble(nsteps=nsteps)
+    members = synth.ensemble(members=members, n_scale=n_scale, nsteps=nsteps)
     offs = np.cumsum([0] + [m.n for m in members])
     cat = lambda key, axis: np.ascontiguousarray(
         np.concatenate([getattr(m, key) for m in members], axis=axis))
