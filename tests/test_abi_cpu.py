@@ -121,3 +121,23 @@ def test_null_arguments_rejected_before_device_use(lib):
     assert lib.steps_sync(None) == st.STEPS_E_INVAL
     assert lib.steps_ctx_destroy(None) == st.STEPS_OK
     assert lib.steps_forces_ctx(None, None, None, None, 4, None) == st.STEPS_E_INVAL
+
+
+def test_null_context_rejected_by_newer_entry_points(lib):
+    d = ctypes.c_double()
+    i64 = ctypes.c_int64()
+    k = st.Cosmology().to_c()
+    t = st.steps_tile(1, 128, 1, 0)
+    out = (ctypes.c_double * 7)()
+    E = st.STEPS_E_INVAL
+    assert lib.steps_kinetic_ctx(None, None, None, 4, 1.0, out) == E
+    assert lib.steps_energy_ctx(None, None, None, None, None, 4, 1.0, ctypes.byref(k), out) == E
+    assert lib.steps_adaptive_dt_ctx(None, None, None, None, None, 4, 1.0, ctypes.byref(k),
+                                     1e-2, 1.0, ctypes.byref(d), ctypes.byref(d)) == E
+    assert lib.steps_run_adaptive_ctx(None, None, None, None, None, 4, None, 0.1, 0.2,
+                                      ctypes.byref(k), 1e-2, 1.0, 10, ctypes.byref(i64),
+                                      ctypes.byref(d)) == E
+    assert lib.steps_ctx_set_periodic(None, 10.0, 1) == E
+    assert lib.steps_ctx_set_tuned(None, 100, ctypes.byref(t)) == E
+    assert lib.steps_autotune(None, None, None, None, 4, None, ctypes.byref(t)) == E
+    assert lib.steps_batch_tile(None, ctypes.byref(t)) == E

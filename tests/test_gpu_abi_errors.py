@@ -137,3 +137,42 @@ def test_profile_timing_counts_launches(st):
     assert cnt == 3 and ms > 0
     assert ctx.force_timing() == (0.0, 0)
     ctx.close()
+
+
+def test_newer_entry_points_validate_pointers_and_values(st):
+    import torch
+    lib = st.load()
+    ps = synth.config(1, n=200)
+    p, m, h = dev(ps.pos), dev(ps.mass), dev(ps.soft)
+    v = torch.zeros_like(p)
+    acc = st.steps_forces(p, m, h)
+    torch.cuda.synchronize()
+    ctx = st.Context(0)
+    k = st.Cosmology().to_c()
+    d, da = ctypes.c_double(), ctypes.c_double()
+    out = (ctypes.c_double * 4)()
+    host_arr = np.zeros(3 * 200)
+    # kinetic: host velocity, negative n, a <= 0
+    assert lib.steps_kinetic_ctx(ctx.handle, VP(host_arr.ctypes.data), _p(m), 200, 1.0, out) \
+        == st.STEPS_E_INVAL and "vel" in _msg(lib)
+    assert lib.steps_kinetic_ctx(ctx.handle, _p(v), _p(m), -1, 1.0, out) == st.STEPS_E_INVAL
+    assert lib.steps_kinetic_ctx(ctx.handle, _p(v), _p(m), 200, 0.0, out) == st.STEPS_E_INVAL
+    # adaptive step: host acc, eps <= 0, NULL outputs
+    rc = lib.steps_adaptive_dt_ctx(ctx.handle, _p(p), _p(v), _p(h), VP(host_arr.ctypes.data),
+                                   200, 0.5, ctypes.byref(k), 1e-2, 1.0,
+                                   ctypes.byref(d), ctypes.byref(da))
+    assert rc == st.STEPS_E_INVAL and "acc" in _msg(lib)
+    rc = lib.steps_adaptive_dt_ctx(ctx.handle, _p(p), _p(v), _p(h), _p(acc), 200, 0.5,
+                                   ctypes.byref(k), 0.0, 1.0, ctypes.byref(d), ctypes.byref(da))
+    assert rc == st.STEPS_E_INVAL and "eps" in _msg(lib)
+    rc = lib.steps_adaptive_dt_ctx(ctx.handle, _p(p), _p(v), _p(h), _p(acc), 200, 0.5,
+                                   ctypes.byref(k), 1e-2, 1.0, None, ctypes.byref(da))
+    assert rc == st.STEPS_E_INVAL
+    # periodic: bad box, unknown rule
+    assert lib.steps_ctx_set_periodic(ctx.handle, -5.0, 1) == st.STEPS_E_INVAL
+    assert lib.steps_ctx_set_periodic(ctx.handle, 5.0, 7) == st.STEPS_E_INVAL
+    # tuned shape that names no kernel
+    bad = st.steps_tile(3, 128, 1, 0)
+    assert lib.steps_ctx_set_tuned(ctx.handle, 200, ctypes.byref(bad)) == st.STEPS_E_INVAL
+    ctx.close()
+    assert np.array_equal(host(v), np.zeros_like(ps.pos))
