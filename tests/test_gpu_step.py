@@ -183,3 +183,38 @@ def test_mixed_step_close_to_fp64(st, prec):
     dx = np.linalg.norm(res[prec] - res["fp64"], axis=0) / ps.soft
     print("%s vs fp64 after 10 steps: |dx|/h max %.2e" % (prec, dx.max()))
     assert dx.max() < 1e-4
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_checkpoint_resume_is_bitwise(st, prec):
+    # the whole state is (pos, vel, acc): ten steps in one go equal five
+    # steps, a round trip of the state through host memory (a checkpoint),
+    # and five more, bit for bit (no atomics anywhere in the step)
+    import torch
+    ps = synth.config(2, n=40000)
+    grid = ps.a_grid()[:11]
+    _, gc = _pair(st, ps.cosmo)
+    m, h = dev(ps.mass), dev(ps.soft)
+    ctx = st.Context(0, precision=prec)
+    p, v = dev(ps.pos), dev(ps.vel)
+    acc = st.steps_forces(p, m, h, ctx=ctx)
+    for k in range(10):
+        st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], gc, ctx=ctx)
+    whole = [host(t) for t in (p, v, acc)]
+    ctx.close()
+    ctx = st.Context(0, precision=prec)
+    p, v = dev(ps.pos), dev(ps.vel)
+    acc = st.steps_forces(p, m, h, ctx=ctx)
+    for k in range(5):
+        st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], gc, ctx=ctx)
+    saved = [host(t).copy() for t in (p, v, acc)]
+    del p, v, acc
+    ctx.close()
+    torch.cuda.synchronize()
+    ctx = st.Context(0, precision=prec)          # a fresh context resumes
+    p, v, acc = (dev(x) for x in saved)
+    for k in range(5, 10):
+        st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], gc, ctx=ctx)
+    ctx.close()
+    for a, b in zip(whole, (host(p), host(v), host(acc))):
+        assert np.array_equal(a, b)
