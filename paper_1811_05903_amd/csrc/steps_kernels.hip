@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_energy_partial(
   for (int c = 0; c < kEnergySums; ++c) red[c][threadIdx.x] = v[c];
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
+    if ((int)threadIdx.x < w) {
 #pragma unroll
       for (int c = 0; c < kEnergySums; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
     }
@@ -250,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_dt_partial(
   red[threadIdx.x] = q;
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_dt_final(
   red[threadIdx.x] = q;
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = red[0];

@@ -49,7 +49,7 @@ __device__ __noinline__ double soft_w64(double r2, double h, double m) {
   return m * fma(hinv3, p, -(rinv * rinv * rinv) * (1.0 / 15.0));
 }
 
-__device__ __noinline__ float soft_w32(float r2, float h, float m) {
+[[maybe_unused]] __device__ __noinline__ float soft_w32(float r2, float h, float m) {
   if (r2 == 0.0f) return 0.0f;
   float rinv = __builtin_amdgcn_rsqf(r2);
   float r = r2 * rinv;
