@@ -275,7 +275,9 @@ int steps_step(double *pos, double *vel, const double *mass,
  * *da (HOST) the scale-factor step whose cosmic-time interval is *dt (= dt
  * in the Newtonian test mode).  pos, vel, acc [3][n] and soft [n] device;
  * acc must hold S(pos), as steps_step leaves it.  eps and dt_max finite and
- * > 0.  Waits for the result (one device min-reduction). */
+ * > 0.  A particle with zero softening and a nonzero acceleration makes the
+ * step zero: STEPS_E_INVAL.  Waits for the result (one device
+ * min-reduction). */
 int steps_adaptive_dt_ctx(steps_ctx *ctx, const double *pos, const double *vel,
                           const double *soft, const double *acc, int64_t n,
                           double a, const steps_cosmology *cosmo, double eps,

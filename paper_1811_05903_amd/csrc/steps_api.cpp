@@ -1115,6 +1115,11 @@ static int adaptive_impl(steps_ctx *c, const double *pos, const double *vel,
   }
   double dt = dt_max;
   if (std::isfinite(q)) dt = std::min(dt_max, std::sqrt(2.0 * eps * q));
+  if (!(dt > 0.0)) {
+    return fail(STEPS_E_INVAL,
+                "the step of Eq. 12 is zero: a particle with zero softening "
+                "(eta = 2.8 h = 0) has a nonzero acceleration");
+  }
   double da = 0.0;
   if (!make_background(cosmo).da_for_dt(a, dt, &da)) {
     return fail(STEPS_E_INVAL, "no scale-factor step reaches dt = %g Gyr", dt);

@@ -176,3 +176,30 @@ def test_newer_entry_points_validate_pointers_and_values(st):
     assert lib.steps_ctx_set_tuned(ctx.handle, 200, ctypes.byref(bad)) == st.STEPS_E_INVAL
     ctx.close()
     assert np.array_equal(host(v), np.zeros_like(ps.pos))
+
+
+def test_impossible_scratch_allocation_is_reported(st):
+    # 2^25 particles with 1024 forced j-splits need 1024 x 3 x 2^25 x 8 B
+    # (~825 GB) of partials: hipMalloc fails, STEPS_E_NOMEM is returned
+    # before any launch, and the context stays usable
+    import torch
+    n = 1 << 25
+    g = torch.Generator(device="cuda").manual_seed(3)
+    p = torch.rand((3, n), dtype=torch.float64, device="cuda", generator=g)
+    m = torch.ones(n, dtype=torch.float64, device="cuda")
+    h = torch.full((n,), 1e-3, dtype=torch.float64, device="cuda")
+    acc = torch.zeros_like(p)
+    ctx = st.Context(0, precision="fp64")
+    ctx.set_tile(4, 128, 1024, 0)
+    with pytest.raises(st.StepsError) as ei:
+        st.steps_forces(p, m, h, acc=acc, ctx=ctx)
+    assert ei.value.code == st.STEPS_E_NOMEM
+    assert "partial-sum" in str(ei.value)
+    assert bool((acc == 0).all())
+    del p, m, h, acc
+    torch.cuda.empty_cache()
+    ctx.set_tile()                          # back to automatic shapes
+    ps = synth.config(1, n=500)
+    got = st.steps_forces(dev(ps.pos), dev(ps.mass), dev(ps.soft), ctx=ctx)
+    assert bool(torch.isfinite(got).all())
+    ctx.close()

@@ -84,3 +84,13 @@ def test_run_adaptive_cap_and_errors(st):
     z = torch.empty(0, dtype=torch.float64, device="cuda")
     dt, da = st.steps_adaptive_dt(e, e, z, e, 0.03, gc, 1e-2, 0.5)
     assert dt == 0.5 and da > 0.0
+    # zero softening: Eq. 12 gives a zero step (the oracle says 0 as well)
+    h0 = h.clone()
+    h0[5] = 0.0
+    with pytest.raises(st.StepsError) as ei:
+        st.steps_adaptive_dt(p, v, h0, acc, 0.03, gc, 1e-2, 1.0)
+    assert "zero softening" in str(ei.value)
+    oc, _ = _cosmos(st, ps.cosmo)
+    soft0 = ps.soft.copy()
+    soft0[5] = 0.0
+    assert oracle.adaptive_dt(host(p), host(v), soft0, host(acc), 0.03, oc, 1e-2, 1.0)[0] == 0.0

@@ -186,10 +186,10 @@ def test_mixed_step_close_to_fp64(st, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_checkpoint_resume_is_bitwise(st, prec):
+def test_checkpoint_resume_is_bitwise(st, prec, tmp_path):
     # the whole state is (pos, vel, acc): ten steps in one go equal five
-    # steps, a round trip of the state through host memory (a checkpoint),
-    # and five more, bit for bit (no atomics anywhere in the step)
+    # steps, a checkpoint file (paper_1811_05903_amd.checkpoint), a fresh
+    # context and five more, bit for bit (no atomics anywhere in the step)
     import torch
     ps = synth.config(2, n=40000)
     grid = ps.a_grid()[:11]
@@ -207,14 +207,17 @@ def test_checkpoint_resume_is_bitwise(st, prec):
     acc = st.steps_forces(p, m, h, ctx=ctx)
     for k in range(5):
         st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], gc, ctx=ctx)
-    saved = [host(t).copy() for t in (p, v, acc)]
+    from paper_1811_05903_amd import checkpoint
+    path = str(tmp_path / "run.npz")
+    checkpoint.save(path, p, v, acc, grid[5], 5, gc, prec)
     del p, v, acc
     ctx.close()
     torch.cuda.synchronize()
-    ctx = st.Context(0, precision=prec)          # a fresh context resumes
-    p, v, acc = (dev(x) for x in saved)
-    for k in range(5, 10):
-        st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], gc, ctx=ctx)
+    p, v, acc, a, k0, gc2, prec2 = checkpoint.load(path)
+    assert (a, k0, prec2) == (grid[5], 5, prec) and gc2 == gc
+    ctx = st.Context(0, precision=prec2)         # a fresh context resumes
+    for k in range(k0, 10):
+        st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], gc2, ctx=ctx)
     ctx.close()
     for a, b in zip(whole, (host(p), host(v), host(acc))):
         assert np.array_equal(a, b)
