@@ -1209,21 +1209,46 @@ namespace {
 struct BatchLayout {
   std::vector<int> tile_beg, tile_end;   // member-local tiles, slot ranges
   std::vector<int4> items;               // (i0, iend, jbeg, jend)
-  std::vector<int> tbase;                // first tile of the item's member
+  std::vector<int> tbase;                // first tile of the item's j-range
+  std::vector<int> islot;                // j-chunk (output plane) of the item
+  std::vector<int> kc;                   // j-chunks of each member
+  int planes = 1;                        // largest kc
 };
 
-// Tiles of tj slots from each member's start; items of 256 r slots, ordered
-// by member size (the cost of an item), largest first.
+// Work items the persistent ensemble kernel should have to spread evenly
+// over the GPU: a few per resident block.
+constexpr int64_t kBatchTargetItems = 8192;
+
+// Tiles of tj slots from each member's start; items of 256 r slots.  When
+// the ensemble gives fewer than kBatchTargetItems such blocks, each member's
+// j-range is also split into up to K tile-aligned chunks (K = target / items,
+// at most 64, never below one tile per chunk); an item then covers one
+// (i-block, j-chunk) and writes its own output plane, the planes being
+// summed in order afterwards.  Items are ordered by member size (the cost of
+// an item), largest first.
 BatchLayout batch_layout(const std::vector<int> &soff, int r, int tj) {
   BatchLayout L;
   const int A = (int)soff.size() - 1;
   std::vector<int> mtb(A);
+  int64_t blocks = 0;
   for (int a = 0; a < A; ++a) {
     mtb[a] = (int)L.tile_beg.size();
     for (int k = soff[a]; k < soff[a + 1]; k += tj) {
       L.tile_beg.push_back(k);
       L.tile_end.push_back(std::min(k + tj, soff[a + 1]));
     }
+    blocks += (soff[a + 1] - soff[a] + 256LL * r - 1) / (256LL * r);
+  }
+  const int K = (int)std::min<int64_t>(
+      64, std::max<int64_t>(1, (kBatchTargetItems + blocks - 1) / std::max<int64_t>(1, blocks)));
+  L.kc.assign(A, 1);
+  std::vector<int> per(A, 1);
+  for (int a = 0; a < A; ++a) {
+    const int ntl = (soff[a + 1] - soff[a] + tj - 1) / tj;
+    const int ka = std::max(1, std::min(K, ntl));
+    per[a] = (ntl + ka - 1) / ka;                  // tiles per chunk
+    L.kc[a] = std::max(1, (ntl + per[a] - 1) / per[a]);  // all non-empty
+    L.planes = std::max(L.planes, L.kc[a]);
   }
   std::vector<int> order(A);
   for (int a = 0; a < A; ++a) order[a] = a;
@@ -1232,9 +1257,14 @@ BatchLayout batch_layout(const std::vector<int> &soff, int r, int tj) {
   });
   for (int a : order) {
     for (int i0 = soff[a]; i0 < soff[a + 1]; i0 += 256 * r) {
-      L.items.push_back(make_int4(i0, std::min(i0 + 256 * r, soff[a + 1]),
-                                  soff[a], soff[a + 1]));
-      L.tbase.push_back(mtb[a]);
+      const int iend = std::min(i0 + 256 * r, soff[a + 1]);
+      for (int c = 0; c < L.kc[a]; ++c) {
+        const int jbeg = soff[a] + c * per[a] * tj;
+        const int jend = std::min(soff[a + 1], jbeg + per[a] * tj);
+        L.items.push_back(make_int4(i0, iend, jbeg, jend));
+        L.tbase.push_back(mtb[a] + c * per[a]);
+        L.islot.push_back(c);
+      }
     }
   }
   return L;
@@ -1253,6 +1283,8 @@ struct BatchDev {
   double *info, *table, *bpart, *box;
   int *tile_beg, *tile_end, *tbase, *counter;
   int4 *items;
+  int *islot, *kc;
+  double *part;  // [planes][3][N] j-chunk partials (planes > 1)
 };
 
 struct BatchRun {
@@ -1261,7 +1293,7 @@ struct BatchRun {
   int N, A, nsteps, cls, kahan;
   BatchDev d;
   const steps::BatchVariant *v = nullptr;
-  int ntiles = 0, nitems = 0;
+  int ntiles = 0, nitems = 0, planes = 1;
 };
 
 hipError_t batch_forces(BatchRun &R) {
@@ -1284,12 +1316,17 @@ hipError_t batch_forces(BatchRun &R) {
   L.stride = R.N;
   L.items = R.d.items;
   L.tbase = R.d.tbase;
+  L.islot = R.planes > 1 ? R.d.islot : nullptr;
   L.nitems = R.nitems;
   L.tinfo = R.d.info;
-  L.out = R.d.acc;
+  L.out = R.planes > 1 ? R.d.part : R.d.acc;
   L.counter = R.d.counter + 1;
   L.kahan = R.kahan;
-  return R.v->launch(L, R.s);
+  e = R.v->launch(L, R.s);
+  if (e == hipSuccess && R.planes > 1) {
+    e = steps::launch_batch_reduce(R.d.part, R.N, R.d.mid, R.d.kc, R.d.acc, R.s);
+  }
+  return e;
 }
 
 // One KDK step; only kernel launches (capturable).
@@ -1365,6 +1402,15 @@ hipError_t upload_layout(BatchRun &R, const BatchLayout &L) {
     e = hipMemcpyAsync(R.d.tbase, L.tbase.data(), L.tbase.size() * sizeof(int),
                        hipMemcpyHostToDevice, R.s);
   }
+  if (e == hipSuccess) {
+    e = hipMemcpyAsync(R.d.islot, L.islot.data(), L.islot.size() * sizeof(int),
+                       hipMemcpyHostToDevice, R.s);
+  }
+  if (e == hipSuccess) {
+    e = hipMemcpyAsync(R.d.kc, L.kc.data(), L.kc.size() * sizeof(int),
+                       hipMemcpyHostToDevice, R.s);
+  }
+  R.planes = L.planes;
   // the host vectors must outlive the copies
   if (e == hipSuccess) e = hipStreamSynchronize(R.s);
   return e;
@@ -1562,7 +1608,12 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
                                    nullptr, nullptr, N, c->stream);
   if (e != hipSuccess) return hip_fail(e, "radix sort size query");
   const size_t max_tiles = (size_t)N / 128 + A + 1;
-  const size_t max_items = (size_t)N / 256 + A + 1;
+  size_t max_items = 1, max_planes = 1;
+  for (const auto *v : cands) {  // every layout the run may use
+    const BatchLayout L = batch_layout(soff, v->r, v->tj);
+    max_items = std::max(max_items, L.items.size());
+    max_planes = std::max(max_planes, (size_t)L.planes);
+  }
   const size_t n = (size_t)N, d8 = sizeof(double);
   Carve cv;
   const size_t o_pos = cv.take(3 * n * d8), o_vel = cv.take(3 * n * d8),
@@ -1581,6 +1632,8 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
                o_box = cv.take(6 * d8), o_tb = cv.take(max_tiles * 4),
                o_te = cv.take(max_tiles * 4), o_tbase = cv.take(max_items * 4),
                o_items = cv.take(max_items * sizeof(int4)),
+               o_islot = cv.take(max_items * 4), o_kc = cv.take((size_t)A * 4),
+               o_part = cv.take(max_planes > 1 ? max_planes * 3 * n * d8 : 0),
                o_cnt = cv.take(2 * 4);
   if ((rc = ensure(c, c->arena, cv.off, "ensemble"))) return rc;
   char *base = (char *)c->arena.p;
@@ -1613,6 +1666,9 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
   d.tile_end = (int *)(base + o_te);
   d.tbase = (int *)(base + o_tbase);
   d.items = (int4 *)(base + o_items);
+  d.islot = (int *)(base + o_islot);
+  d.kc = (int *)(base + o_kc);
+  d.part = max_planes > 1 ? (double *)(base + o_part) : nullptr;
   d.counter = (int *)(base + o_cnt);
 
   // the run uses its own stream (graph capture needs one), ordered after

@@ -71,6 +71,21 @@ __global__ __launch_bounds__(kBlock) void k_batch_kick_end(
   }
 }
 
+// acc[d][i] = sum over the j-chunk planes c < kc[member of i] of
+// part[c][d][i], in plane order (deterministic)
+__global__ __launch_bounds__(kBlock) void k_batch_reduce(
+    const double *__restrict__ part, int n, const int *__restrict__ mid,
+    const int *__restrict__ kc, double *__restrict__ acc) {
+  const size_t total = 3 * (size_t)n;
+  const size_t q = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= total) return;
+  const int i = (int)(q % (size_t)n);
+  const int k = kc[mid[i]];
+  double s = 0.0;
+  for (int c = 0; c < k; ++c) s += part[(size_t)c * total + q];
+  acc[q] = s;
+}
+
 __global__ void k_batch_advance(int *counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] += 1;
 }
@@ -207,6 +222,14 @@ hipError_t launch_batch_kick_end(const double *pos, double *vel,
   hipLaunchKernelGGL(k_batch_kick_end, dim3(ceil_div(std::max(n, 1), kBlock)),
                      dim3(kBlock), 0, s, pos, vel, S, mid, n, table, members,
                      nsteps, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce(const double *part, int n, const int *mid,
+                               const int *kc, double *acc, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reduce,
+                     dim3(ceil_div(std::max(3LL * n, 1LL), kBlock)), dim3(kBlock),
+                     0, s, part, n, mid, kc, acc);
   return hipGetLastError();
 }
 

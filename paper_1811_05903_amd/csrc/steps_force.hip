@@ -607,8 +607,10 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(
 // Ensemble kernels: a persistent grid pulls work items from an atomic
 // counter until none are left (every block then returns, so the grid always
 // drains).  Item k is the block of particles [it.x, it.y) of one member
-// against that member's whole range [it.z, it.w); tbase[k] is the index of
-// the member's first tile in tinfo.  Items are ordered longest first.
+// against a tile-aligned part [it.z, it.w) of that member's range (all of
+// it, or one of its j-chunks); tbase[k] is the index of that part's first
+// tile in tinfo, and islot[k] (if given) the output plane the item writes,
+// one plane per j-chunk, reduced afterwards in fixed order.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int next_item(int *counter, int *slot) {
   __syncthreads();  // everyone has read the previous item
@@ -621,15 +623,16 @@ template <int R, int TJ, bool E2>
 __global__ __launch_bounds__(kBlock) void k_batch_force_f64(
     const double *__restrict__ pos, const double *__restrict__ mass,
     const double *__restrict__ soft, int stride, const int4 *__restrict__ items,
-    const int *__restrict__ tbase, int nitems,
+    const int *__restrict__ tbase, const int *__restrict__ islot, int nitems,
     const double *__restrict__ tinfo, double *__restrict__ out, int *counter) {
   __shared__ double2 tile[3 * TJ];
   __shared__ int slot;
   for (int it = next_item(counter, &slot); it < nitems;
        it = next_item(counter, &slot)) {
     const int4 w = items[it];
+    double *o = islot ? out + (size_t)islot[it] * 3 * (size_t)stride : out;
     force_block_f64<R, TJ, E2, true>(pos, mass, soft, stride, w.x, w.y, w.z,
-                                     w.w, tinfo + (size_t)tbase[it] * 8, out,
+                                     w.w, tinfo + (size_t)tbase[it] * 8, o,
                                      tile);
   }
 }
@@ -638,7 +641,7 @@ template <int TJ>
 __global__ __launch_bounds__(kBlock) void k_batch_force_f64_mfma(
     const double *__restrict__ pos, const double *__restrict__ mass,
     const double *__restrict__ soft, int stride, const int4 *__restrict__ items,
-    const int *__restrict__ tbase, int nitems,
+    const int *__restrict__ tbase, const int *__restrict__ islot, int nitems,
     const double *__restrict__ tinfo, double *__restrict__ out, int *counter) {
   __shared__ double2 tile[3 * TJ];
   __shared__ double gram[4 * TJ];
@@ -647,8 +650,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_force_f64_mfma(
   for (int it = next_item(counter, &slot); it < nitems;
        it = next_item(counter, &slot)) {
     const int4 w = items[it];
+    double *o = islot ? out + (size_t)islot[it] * 3 * (size_t)stride : out;
     force_block_f64_mfma<TJ>(pos, mass, soft, stride, w.x, w.y, w.z, w.w,
-                             tinfo + (size_t)tbase[it] * 8, out, tile, gram,
+                             tinfo + (size_t)tbase[it] * 8, o, tile, gram,
                              bmat);
   }
 }
@@ -656,7 +660,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_force_f64_mfma(
 template <int R, int TJ, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_batch_force_mixed(
     const float *__restrict__ shadow, int stride, const int4 *__restrict__ items,
-    const int *__restrict__ tbase, int nitems,
+    const int *__restrict__ tbase, const int *__restrict__ islot, int nitems,
     const double *__restrict__ tinfo, double *__restrict__ out, int *counter) {
   __shared__ float4 tpos[TJ];
   __shared__ float tsoft[TJ];
@@ -664,8 +668,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_force_mixed(
   for (int it = next_item(counter, &slot); it < nitems;
        it = next_item(counter, &slot)) {
     const int4 w = items[it];
+    double *o = islot ? out + (size_t)islot[it] * 3 * (size_t)stride : out;
     force_block_mixed<R, TJ, KAHAN, true>(shadow, stride, w.x, w.y, w.z, w.w,
-                                          tinfo + (size_t)tbase[it] * 8, out,
+                                          tinfo + (size_t)tbase[it] * 8, o,
                                           tpos, tsoft);
   }
 }
@@ -724,7 +729,7 @@ template <int R, int TJ, bool E2>
 hipError_t launch_batch_f64(const BatchLaunch &L, hipStream_t s) {
   static const int grid = persistent_grid(k_batch_force_f64<R, TJ, E2>);
   hipLaunchKernelGGL((k_batch_force_f64<R, TJ, E2>), dim3(grid), dim3(kBlock),
-                     0, s, L.pos, L.mass, L.soft, L.stride, L.items, L.tbase,
+                     0, s, L.pos, L.mass, L.soft, L.stride, L.items, L.tbase, L.islot,
                      L.nitems, L.tinfo, L.out, L.counter);
   return hipGetLastError();
 }
@@ -733,7 +738,7 @@ template <int TJ>
 hipError_t launch_batch_f64_mfma(const BatchLaunch &L, hipStream_t s) {
   static const int grid = persistent_grid(k_batch_force_f64_mfma<TJ>);
   hipLaunchKernelGGL((k_batch_force_f64_mfma<TJ>), dim3(grid), dim3(kBlock), 0,
-                     s, L.pos, L.mass, L.soft, L.stride, L.items, L.tbase,
+                     s, L.pos, L.mass, L.soft, L.stride, L.items, L.tbase, L.islot,
                      L.nitems, L.tinfo, L.out, L.counter);
   return hipGetLastError();
 }
@@ -744,12 +749,12 @@ hipError_t launch_batch_mixed(const BatchLaunch &L, hipStream_t s) {
     static const int grid = persistent_grid(k_batch_force_mixed<R, TJ, true>);
     hipLaunchKernelGGL((k_batch_force_mixed<R, TJ, true>), dim3(grid),
                        dim3(kBlock), 0, s, L.shadow, L.stride, L.items,
-                       L.tbase, L.nitems, L.tinfo, L.out, L.counter);
+                       L.tbase, L.islot, L.nitems, L.tinfo, L.out, L.counter);
   } else {
     static const int grid = persistent_grid(k_batch_force_mixed<R, TJ, false>);
     hipLaunchKernelGGL((k_batch_force_mixed<R, TJ, false>), dim3(grid),
                        dim3(kBlock), 0, s, L.shadow, L.stride, L.items,
-                       L.tbase, L.nitems, L.tinfo, L.out, L.counter);
+                       L.tbase, L.islot, L.nitems, L.tinfo, L.out, L.counter);
   }
   return hipGetLastError();
 }

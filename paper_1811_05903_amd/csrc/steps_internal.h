@@ -46,10 +46,11 @@ struct BatchLaunch {
   const float *shadow = nullptr;  // mixed: [5][stride]
   int stride = 0;                 // total particles of the ensemble
   const int4 *items = nullptr;    // (i0, iend, jbeg, jend) per work item
-  const int *tbase = nullptr;     // first tile of the item's member
+  const int *tbase = nullptr;     // first tile of the item's j-range
+  const int *islot = nullptr;     // output plane of each item (NULL: all 0)
   int nitems = 0;
   const double *tinfo = nullptr;  // [tiles][8]
-  double *out = nullptr;          // [3][stride]
+  double *out = nullptr;          // [planes][3][stride]
   int *counter = nullptr;         // work counter, 0 before the launch
   int kahan = 0;
 };
@@ -73,6 +74,10 @@ hipError_t launch_batch_kick_end(const double *pos, double *vel,
                                  const double *S, const int *mid, int n,
                                  const double *table, int members, int nsteps,
                                  const int *counter, hipStream_t s);
+// acc <- sum of the j-chunk planes of part ([planes][3][n]), kc[member]
+// planes for the particles of each member, in plane order
+hipError_t launch_batch_reduce(const double *part, int n, const int *mid,
+                               const int *kc, double *acc, hipStream_t s);
 hipError_t launch_batch_advance(int *counter, hipStream_t s);
 hipError_t launch_batch_tile_info_f64(const double *soa, int stride,
                                       const int *beg, const int *end,
