@@ -71,9 +71,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU "
+        print("bench.py runs on one GPU only: the library has no multi-GPU "
               "path (each GPU would own a block of i-rows and all-gather "
-              "positions once per step; see the design notes).",
+              "positions once per step).",
               file=sys.stderr)
         sys.exit(2)
 

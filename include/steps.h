@@ -54,7 +54,7 @@ extern "C" {
 #define STEPS_E_NOMEM (-2)       /* device scratch allocation failed */
 #define STEPS_E_HIP (-3)         /* HIP runtime error; message has the text */
 #define STEPS_E_NONFINITE (-4)   /* non-finite input (STEPS_CHECK_FINITE) */
-#define STEPS_E_UNSUPPORTED (-5) /* option not available in this build */
+#define STEPS_E_UNSUPPORTED (-5) /* option not supported by this mode/call */
 
 /* ---- precision modes (steps_ctx_set_precision) ------------------------ */
 /* FP64 throughout; deterministic (fixed summation order, no atomics). */

@@ -15,8 +15,7 @@
  * (Neumaier) sums so that the oracle's own rounding stays far below the GPU
  * tolerance.  Build with -O2 -ffp-contract=off and no fast-math.
  *
- * Readings of points the paper leaves open (each is also listed in the
- * design notes):
+ * Readings of points the paper leaves open:
  *   - The three branches of the spline kernel (Sec. 2.2, Eq. 4) use strict
  *     inequalities at r = h/2 and r = h; here u < 1/2 is the inner branch,
  *     1/2 <= u < 1 the middle one and u >= 1 the Newtonian one.  Value and
