@@ -156,8 +156,8 @@ def main():
         # the FP64 matrix-core kernel and the vector kernels are both priced
         # at the FP64 peak: on gfx950 dense FP64 MFMA and FP64 VALU share one
         # 78.6 TFLOP/s pipe
-        "roofline": {"bound": "mfma" if force_kernel_name(args.precision, tile)
-                     .endswith("mfma") else "alu",
+        "roofline": {"bound": "mfma" if tile["variant"] & 4
+                     and args.precision == "fp64" else "alu",
                      "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic,
@@ -225,6 +225,8 @@ def force_kernel_name(precision, tile):
     """Name of the force kernel a launch shape runs (as rocprofv3 lists it)."""
     if precision != "fp64":
         return "k_force_mixed"
+    if tile["variant"] & 8:
+        return "k_force_f64_sym"
     return "k_force_f64_mfma" if tile["variant"] & 4 else "k_force_f64"
 
 

@@ -109,10 +109,21 @@ typedef struct steps_cosmology {
 
 /* Launch shape of the force kernels.  r: i-particles held per lane;
  * tj: j-particles per LDS tile; jsplit: number of j-ranges the sum is split
- * into (partials reduced in fixed order); variant: kernel option -- for
- * STEPS_FP64, 0 evaluates r^-3 from v_rsq_f64 with a second-order
- * correction, 1 with a first-order one (one instruction less per pair,
- * ~1e-15 typical extra relative error); mixed modes accept only 0. */
+ * into (partials reduced in fixed order; 0 in a forced shape = the built-in
+ * choice for each n); variant: kernel option bits --
+ *   1  STEPS_FP64 only: r^-3 from v_rsq_f64 with a first-order correction
+ *      instead of a second-order one (one instruction less per pair, ~1e-15
+ *      typical extra relative error);
+ *   2  particles sorted along a space-filling curve inside the call, and the
+ *      softening test skipped for (wave, tile) blocks whose boxes are
+ *      farther apart than their largest combined softening;
+ *   4  STEPS_FP64, with 2: well-separated blocks on the matrix cores
+ *      (r = 1; tj 128 or 256);
+ *   8  STEPS_FP64, with 2 and 4: each pair between two different chunks of
+ *      the sorted set evaluated once and applied to both particles (Newton's
+ *      third law; r = 1, tj = 256); jsplit is then the number of chunks.
+ * Compiled combinations: FP64 0, 1, 2, 3 (r 1, 2, 4, 8; tj 128), 6 (tj 128
+ * and 256), 14 (tj 256); mixed modes 0 and 2. */
 typedef struct steps_tile {
   int32_t r;
   int32_t tj;
@@ -141,8 +152,8 @@ int steps_ctx_set_stream(steps_ctx *ctx, void *stream);
 int steps_ctx_set_precision(steps_ctx *ctx, int precision);
 int steps_ctx_set_flags(steps_ctx *ctx, uint32_t flags);
 /* Force a launch shape (validated against the compiled variants; r and tj
- * must name one of them, jsplit >= 1).  Passing NULL returns to automatic
- * selection (tuned table, else heuristic). */
+ * must name one of them, 0 <= jsplit <= 1024).  Passing NULL returns to
+ * automatic selection (tuned table, else heuristic). */
 int steps_ctx_set_tile(steps_ctx *ctx, const steps_tile *tile);
 /* Periodic box (Sec. 2.2, Eqs. 2 and 5).  With images != NONE every pair
  * sum on this context (steps_forces_ctx, steps_step_ctx, the adaptive step)

@@ -29,6 +29,7 @@ constexpr int64_t kMaxN = int64_t(1) << 30;
 // below this size the spatial sort costs more than the culling saves
 constexpr int64_t kSortMinN = 32768;
 constexpr int64_t kMfmaMinN = 131072;
+constexpr int64_t kSymMinN = 262144;
 
 thread_local std::string t_err;
 
@@ -180,11 +181,33 @@ int variant_tj(int cls, int r) {
   return 0;
 }
 
+// Chunk count Q of the symmetric kernel (Q (Q + 1) / 2 units (R, s),
+// R <= s, of chunk pairs, one workgroup each).  Units are equal, so the
+// last round of workgroups runs part-empty; measured on MI355X, more and
+// smaller units win until chunks of about 1024 particles (N = 2^18: 34.9 ms
+// at Q = 64, 32.5 ms at Q = 256; N = 2^20: 458 ms from Q = 160 on).  So:
+// the largest Q up to 192 with chunks of at least 1024 particles and the
+// partial sums (24 n Q + 48 C Q (Q - 1) / 2 bytes) under 16 GiB.
+int sym_chunks(int64_t n) {
+  const double cap = 16.0 * (1ull << 30);
+  int best = 1;
+  for (int want = 1; want <= 192; ++want) {
+    int64_t c = (n + want - 1) / want;
+    c = std::max<int64_t>(256, (c + 255) / 256 * 256);
+    const int q = (int)((n + c - 1) / c);
+    const double bytes = 24.0 * n * q + 48.0 * c * q * (q - 1) / 2.0;
+    if (q > 1 && (c < 1024 || bytes > cap)) break;
+    best = want;
+  }
+  return best;
+}
+
 // j-split for an (r, tj, variant) shape: enough splits that the grid holds
 // about 8192 (FP64 VALU), 16384 (mixed) or 65536 (FP64 matrix-core; its
 // blocks are a quarter the size) workgroups, keeping every split at least
 // two tiles.
 int heuristic_jsplit(int cls, int64_t n, int r, int tj, int variant) {
+  if (variant & steps::kVarSym) return sym_chunks(n);
   const int64_t nb = std::max<int64_t>(1, (n + 256LL * r - 1) / (256LL * r));
   const int64_t target = cls != steps::kClassF64 ? 16384
                          : (variant & steps::kVarMfma) ? 65536 : 8192;
@@ -195,6 +218,8 @@ int heuristic_jsplit(int cls, int64_t n, int r, int tj, int variant) {
 
 // Launch shape: a forced tile, else a shape tuned for (class, n), else the
 // heuristic, measured on MI355X at N = 2^15 ... 2^21:
+//   * FP64 from kSymMinN up: the symmetric matrix-core kernel (variant 14),
+//     7% ahead of the one-sided one at 2^18 and 17% at 2^20 and 2^21;
 //   * FP64 from kMfmaMinN up: the matrix-core kernel (variant 6, tj 256),
 //     5-7% ahead of the VALU kernel there and 7% behind it at 2^15;
 //   * otherwise FP64 r = 4, mixed r = 2 (fewer registers, more waves to pair
@@ -210,12 +235,17 @@ steps_tile choose_tile(const steps_ctx *c, int64_t n) {
       return e.second;
     }
   }
-  if (c->tile_forced) return c->tile;
+  if (c->tile_forced) {
+    t = c->tile;
+    if (t.jsplit == 0) t.jsplit = heuristic_jsplit(cls, n, t.r, t.tj, t.variant);
+    return t;
+  }
   const bool f64 = cls == steps::kClassF64;
   if (f64 && n >= kMfmaMinN) {
     t.r = 1;
     t.tj = 256;
     t.variant = steps::kVarCull | steps::kVarMfma;
+    if (n >= kSymMinN) t.variant |= steps::kVarSym;
   } else {
     int r = f64 ? 4 : 2;
     while (r > 1 && (n + 256LL * r - 1) / (256LL * r) < 256) r /= 2;
@@ -327,6 +357,7 @@ int run_forces(steps_ctx *c, const double *pos, const double *mass,
                 t.tj, t.variant);
   }
   const bool cull = (t.variant & steps::kVarCull) != 0;
+  const bool sym = (t.variant & steps::kVarSym) != 0;
   int chunk = 0, js = 1;
   split_j(n, t.tj, std::max(1, t.jsplit), &chunk, &js);
   steps::ForceLaunch L;
@@ -361,6 +392,10 @@ int run_forces(steps_ctx *c, const double *pos, const double *mass,
     const size_t o_soa = cv.take(cls == steps::kClassF64
                                      ? 5 * (size_t)n * sizeof(double)
                                      : 5 * (size_t)n * sizeof(float));
+    // symmetric variant: one (value, error) accumulator per off-diagonal unit
+    const size_t o_jacc = cv.take(
+        sym ? (size_t)js * (js - 1) / 2 * 6 * (size_t)chunk * sizeof(double)
+            : 0);
     if ((rc = ensure(c, c->arena, cv.off, "sort"))) return rc;
     char *base = (char *)c->arena.p;
     double *box = (double *)(base + o_box);
@@ -399,6 +434,7 @@ int run_forces(steps_ctx *c, const double *pos, const double *mass,
     }
     if (e != hipSuccess) return hip_fail(e, "gather kernel launch");
     L.tinfo = info;
+    if (sym && js > 1) L.jacc = (double *)(base + o_jacc);
   } else if (cls == steps::kClassMixed) {
     rc = ensure(c, c->shadow, 5 * (size_t)n * sizeof(float), "FP32 shadow");
     if (rc) return rc;
@@ -416,7 +452,11 @@ int run_forces(steps_ctx *c, const double *pos, const double *mass,
   e = v->launch(L, c->stream);
   if (e != hipSuccess) return hip_fail(e, "force kernel launch");
   if ((rc = prof_end(c, ev))) return rc;
-  if (cull) {
+  if (sym) {
+    e = steps::launch_reduce_sym(L.out, L.jacc, n, chunk, js, perm, acc,
+                                 c->stream);
+    if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
+  } else if (cull) {
     e = steps::launch_reduce_scatter(L.out, js, n, perm, acc, c->stream);
     if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
   } else if (js > 1) {
@@ -651,8 +691,8 @@ int steps_ctx_set_tile(steps_ctx *c, const steps_tile *t) {
                 "precision",
                 t->r, t->tj, t->variant);
   }
-  if (t->jsplit < 1 || t->jsplit > 1024) {
-    return fail(STEPS_E_INVAL, "jsplit must be in [1, 1024]");
+  if (t->jsplit < 0 || t->jsplit > 1024) {
+    return fail(STEPS_E_INVAL, "jsplit must be in [0, 1024]");
   }
   c->tile = *t;
   c->tile_forced = true;
@@ -787,21 +827,26 @@ int steps_autotune(steps_ctx *c, const double *pos, const double *mass,
     return STEPS_OK;
   }
   // candidates: every compiled kernel of the class with r in {1, 2, 4}
-  // that the heuristic could choose (FP64 variants 0, 3 and 6, mixed 0 and
-  // 2), each at its heuristic j-split times 1/2, 1 and 2
+  // that the heuristic could choose (FP64 variants 0, 3, 6 and, from
+  // kMfmaMinN, 14; mixed 0 and 2), each at its heuristic j-split times 1/2,
+  // 1 and 2 (the symmetric kernel's chunk count only times 1/2 and 1: its
+  // heuristic count is already the largest within the memory cap)
   std::vector<steps_tile> cands;
   int nvar = 0;
   const steps::ForceVariant *vt = steps::force_variants(&nvar);
   for (int q = 0; q < nvar; ++q) {
     const steps::ForceVariant &v = vt[q];
-    const bool usable = cls == steps::kClassF64
-                            ? (v.variant == 0 || v.variant == 3 || v.variant == 6)
-                            : (v.variant == 0 || v.variant == 2);
+    const bool sym = (v.variant & steps::kVarSym) != 0;
+    const bool usable =
+        cls == steps::kClassF64
+            ? (v.variant == 0 || v.variant == 3 || v.variant == 6 ||
+               (sym && n >= kMfmaMinN))
+            : (v.variant == 0 || v.variant == 2);
     if (v.cls != cls || !usable || (v.r != 1 && v.r != 2 && v.r != 4)) continue;
     const int hj = heuristic_jsplit(cls, n, v.r, v.tj, v.variant);
     {
       const int r = v.r, tj = v.tj, var = v.variant;
-      for (int js : {std::max(1, hj / 2), hj, std::min(1024, 2 * hj)}) {
+      for (int js : {std::max(1, hj / 2), hj, sym ? hj : std::min(1024, 2 * hj)}) {
         const steps_tile t = {r, tj, js, var};
         bool dup = false;
         for (const auto &q : cands) {

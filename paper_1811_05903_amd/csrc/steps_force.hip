@@ -253,6 +253,30 @@ __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
+// every lane of a quad (4 consecutive lanes) takes the quad's lane 3 (DPP
+// quad_perm [3, 3, 3, 3])
+__device__ __forceinline__ double quad_bcast3(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, 0xFF, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0xFF, 0xF,
+                                          0xF, true);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) |
+                              (unsigned)lo);
+}
+
+// v rotated right by N lanes within each row of 16 lanes (DPP row_ror)
+template <int N>
+__device__ __forceinline__ double row_ror(double v) {
+  static_assert(N > 0 && N < 16, "row_ror takes 1..15");
+  const unsigned long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, 0x120 + N, 0xF,
+                                          0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0x120 + N,
+                                          0xF, 0xF, true);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) |
+                              (unsigned)lo);
+}
+
 template <int TJ>
 __device__ __forceinline__ void force_block_f64_mfma(
     const double *__restrict__ pos, const double *__restrict__ mass,
@@ -414,6 +438,305 @@ __device__ __forceinline__ void force_block_f64_mfma(
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) two_sum_add(sum[r], cmp[r], part[r]);
+  }
+
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int id = wbase + 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
+    if (cc < 3 && id < iend) out[(size_t)cc * stride + id] = sum[r] + cmp[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric FP64 evaluation (Newton's third law).  The pair term of Eq. 8
+// is antisymmetric: the pull of j on i is m_j F/r (x_j - x_i) and that of
+// i on j is m_i F/r (x_i - x_j), with the same F(r, h_i + h_j)/r.  The sorted
+// particles are cut into chunks of C (a multiple of 256) and a workgroup
+// takes one unit (R, s), R <= s, of chunk pairs.  For R < s it evaluates
+// each pair of chunk R x chunk s once and keeps both sides:
+//   * i-side (chunk R): the weights summed against (m_j u_j, m_j) in
+//     registers, as in force_block_f64_mfma, written to plane s of iplane;
+//   * j-side (chunk s): the same weights summed against (m_i u_i, m_i).  In
+//     the matrix-core path pair (i, j) sits in lane n + 4b + 16m, i the
+//     row n of block b and j the row m; a product on v_mfma_f64_4x4x4_4b
+//     contracts over the high lane index, so the weights are transposed
+//     within each 4 x 4 block (lane permute) before the second product, and
+//     the four blocks' partials are added across lanes.  A near block runs
+//     the direct loop a second time with the roles swapped (lane = j).
+//     Each wave leaves its per-tile j sums in LDS; after the tile they are
+//     added in wave order and then into the unit's compensated accumulator
+//     (value, error) [6][C] in global memory, which only this workgroup
+//     touches.
+// A diagonal unit (R == s) sums its chunk one-sided into plane s.  Every
+// output word has one writer and a fixed order of additions, so a launch
+// shape gives a bitwise-reproducible result.
+// ---------------------------------------------------------------------------
+template <int TJ>
+__device__ __forceinline__ void sym_block_f64(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ soft, int stride, int i0, int iend, int jbeg,
+    int jend, const double *__restrict__ tinfo, double *__restrict__ out,
+    double *__restrict__ jacc, int chunk, bool first, double2 *tile,
+    double *gram, double *bmat, double *jbuf) {
+  static_assert(TJ == kBlock, "one thread per tile particle in the j-side sum");
+  const int tid = threadIdx.x;
+  const int l = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wbase = i0 + wv * 64;
+  const int last = iend - 1;
+  const int nw = max(0, min(64, iend - wbase));  // valid i of this wave
+  const double *X = pos, *Y = pos + stride, *Z = pos + 2 * (size_t)stride;
+  double *jb = jbuf + (size_t)wv * TJ * 3;  // this wave's [TJ][3] j sums
+
+  const bool valid = wbase + l < iend;
+  const int ip = min(wbase + l, last);
+  const double xi = X[ip], yi = Y[ip], zi = Z[ip], hi = soft[ip];
+  // matrix path roles as in force_block_f64_mfma; lane l also holds the mass
+  // of particle 16 r + 4 ((l >> 2) & 3) + (l >> 4) (zero past iend, so that
+  // padding lanes add nothing to the j-side)
+  const int kk = l >> 4, cc = l & 3;
+  const double *Pc = cc == 0 ? X : (cc == 1 ? Y : Z);
+  // (the operand-layout coordinates and masses are re-read from cache per
+  // tile rather than held, to keep the register count at three waves)
+  double dc[4], sum[4], cmp[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int id = wbase + 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
+    dc[r] = cc < 3 ? Pc[min(id, last)] : 0.0;
+    sum[r] = cmp[r] = 0.0;
+  }
+  double wb[7];
+  {
+    const double xs[1] = {xi}, ys[1] = {yi}, zs[1] = {zi}, hs[1] = {hi};
+    const bool vs[1] = {valid};
+    wave_box<1, double>(xs, ys, zs, hs, vs, wb);
+  }
+  const double wc[3] = {0.5 * (wb[0] + wb[3]), 0.5 * (wb[1] + wb[4]),
+                        0.5 * (wb[2] + wb[5])};
+  const double we = 0.5 * sqrt((wb[3] - wb[0]) * (wb[3] - wb[0]) +
+                               (wb[4] - wb[1]) * (wb[4] - wb[1]) +
+                               (wb[5] - wb[2]) * (wb[5] - wb[2]));
+  // transpose within 4 x 4 blocks: lane n + 4b + 16m reads n' = m, m' = n
+  const int tsrc = ((l >> 4) & 3) | (l & 12) | ((l & 3) << 4);
+
+  for (int jt = jbeg; jt < jend; jt += TJ) {
+    const double *ti = tinfo + (size_t)((jt - jbeg) / TJ) * 8;
+    const double ct[3] = {0.5 * (ti[0] + ti[3]), 0.5 * (ti[1] + ti[4]),
+                          0.5 * (ti[2] + ti[5])};
+    __syncthreads();
+    for (int k = tid; k < TJ; k += kBlock) {
+      const int j = min(jt + k, jend - 1);
+      const double mj = (jt + k < jend) ? mass[j] : 0.0;
+      const double xj = X[j], yj = Y[j], zj = Z[j];
+      tile[3 * k] = double2{xj, yj};
+      tile[3 * k + 1] = double2{zj, mj};
+      tile[3 * k + 2] = double2{soft[j], 0.0};
+      const double ux = xj - ct[0], uy = yj - ct[1], uz = zj - ct[2];
+      const double mm = -1.5 * mj;
+      gram[4 * k] = ux;
+      gram[4 * k + 1] = uy;
+      gram[4 * k + 2] = uz;
+      gram[4 * k + 3] = fma(uz, uz, fma(uy, uy, ux * ux));
+      bmat[4 * k] = mm * ux;
+      bmat[4 * k + 1] = mm * uy;
+      bmat[4 * k + 2] = mm * uz;
+      bmat[4 * k + 3] = mm;
+    }
+    const bool jown = jt + tid < jend;
+    const size_t jl = (size_t)(jt + tid - jbeg);
+    __syncthreads();
+
+    const double gxv = fmax(0.0, fmax(ti[0] - wb[3], wb[0] - ti[3]));
+    const double gyv = fmax(0.0, fmax(ti[1] - wb[4], wb[1] - ti[4]));
+    const double gzv = fmax(0.0, fmax(ti[2] - wb[5], wb[2] - ti[5]));
+    const double d2 = gxv * gxv + gyv * gyv + gzv * gzv;
+    const double hs = ti[6] + wb[6];
+    const bool far = d2 > fmax(hs * hs * (1.0 + 1e-6), 1e-30);
+    const double te = 0.5 * sqrt((ti[3] - ti[0]) * (ti[3] - ti[0]) +
+                                 (ti[4] - ti[1]) * (ti[4] - ti[1]) +
+                                 (ti[5] - ti[2]) * (ti[5] - ti[2]));
+    const double cd = sqrt((wc[0] - ct[0]) * (wc[0] - ct[0]) +
+                           (wc[1] - ct[1]) * (wc[1] - ct[1]) +
+                           (wc[2] - ct[2]) * (wc[2] - ct[2]));
+    const bool sep = far && (cd + we + te) <= kSep * sqrt(d2);
+    const bool use_mfma = __builtin_amdgcn_readfirstlane((int)sep) != 0;
+
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    if (nw == 0) {
+      // a wave past the end of the chunk: nothing on either side
+      for (int k = l; k < 3 * TJ; k += 64) jb[k] = 0.0;
+    } else if (use_mfma) {
+      double b1[4], qi[4], d2acc[4], bi[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ig = min(wbase + 16 * r + (l & 15), last);
+        const double ux = X[ig] - ct[0], uy = Y[ig] - ct[1], uz = Z[ig] - ct[2];
+        const double uk = kk == 0 ? ux : (kk == 1 ? uy : uz);
+        b1[r] = kk < 3 ? -2.0 * uk : 1.0;
+        qi[r] = fma(uz, uz, fma(uy, uy, ux * ux));
+        d2acc[r] = 0.0;
+        const int id = wbase + 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
+        const double m = id < iend ? mass[min(id, last)] : 0.0;
+        const double ctc = cc == 0 ? ct[0] : (cc == 1 ? ct[1] : ct[2]);
+        bi[r] = -1.5 * m * (cc < 3 ? dc[r] - ctc : 1.0);
+      }
+      const int arow = 4 * (l & 3) + kk;
+      const int brow = 4 * kk + cc;
+      // j-side of group g: lane c + 4b + 16m sums, over the i of block b,
+      // w (m_i u_i, m_i)_c for j = 4g + m (two chains of two products);
+      // the four blocks are added with row rotations (DPP), component c < 3
+      // becomes D_c - u_{j,c} D_3 (D_3 broadcast within the quad, u from
+      // gram at the lane's own (m, c)), and lanes b = 0 store.  Pipelined
+      // one group behind the i-side, so that the lane permutes of a group
+      // land while the next one is computed.
+      double wt[4], ujp = 0.0;
+      auto jside = [&](int g) {
+        double j0 = mfma4(wt[0], bi[0], 0.0);
+        double j1 = mfma4(wt[2], bi[2], 0.0);
+        j0 = mfma4(wt[1], bi[1], j0);
+        j1 = mfma4(wt[3], bi[3], j1);
+        double jd = j0 + j1;
+        jd += row_ror<4>(jd);
+        jd += row_ror<8>(jd);
+        const double f = fma(-ujp, quad_bcast3(jd), jd);
+        if ((l & 12) == 0 && cc < 3) jb[3 * (4 * g + kk) + cc] = f;
+      };
+      double a1n = gram[arow], b2n = bmat[brow], ujn = gram[brow];
+#pragma unroll 1
+      for (int g = 0; g < TJ / 4; ++g) {
+        const double a1 = a1n, b2 = b2n;
+        const int gn = min(g + 1, TJ / 4 - 1);
+        a1n = gram[16 * gn + arow];
+        b2n = bmat[16 * gn + brow];
+        double rr[4], w[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rr[r] = mfma4(a1, b1[r], qi[r]);
+        if (g > 0) jside(g - 1);
+        ujp = ujn;
+        ujn = gram[16 * gn + brow];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double y = __builtin_amdgcn_rsq(rr[r]);
+          const double y2 = y * y;
+          const double t = fma(rr[r], y2, -5.0 / 3.0);
+          w[r] = (y * y2) * t;  // -(2/3) r^-3 (1 + 3/2 e)
+          d2acc[r] = mfma4(w[r], b2, d2acc[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wt[r] = __shfl(w[r], tsrc);
+      }
+      jside(TJ / 4 - 1);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double s3 = __shfl(d2acc[r], l | 3);
+        const double ctc = cc == 0 ? ct[0] : (cc == 1 ? ct[1] : ct[2]);
+        const double ui = cc < 3 ? dc[r] - ctc : 0.0;
+        part[r] = fma(-ui, s3, d2acc[r]);
+      }
+    } else {
+      // i-side: lane = i, every j of the tile
+      double tx = 0.0, ty = 0.0, tz = 0.0;
+      if (__builtin_amdgcn_readfirstlane((int)far)) {
+#pragma unroll 4
+        for (int k = 0; k < TJ; ++k) {
+          const double2 a = tile[3 * k], b = tile[3 * k + 1];
+          const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          const double w = newton_w64<true>(r2, b.y);
+          tx = fma(w, dx, tx);
+          ty = fma(w, dy, ty);
+          tz = fma(w, dz, tz);
+        }
+      } else {
+#pragma unroll 2
+        for (int k = 0; k < TJ; ++k) {
+          const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
+          const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          const double h = c.x + hi;
+          double w = newton_w64<true>(r2, b.y);
+          if (r2 <= h * h) w = soft_w64(r2, h, b.y);
+          tx = fma(w, dx, tx);
+          ty = fma(w, dy, ty);
+          tz = fma(w, dz, tz);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int src = 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
+        const double vx = __shfl(tx, src), vy = __shfl(ty, src), vz = __shfl(tz, src);
+        part[r] = cc == 0 ? vx : (cc == 1 ? vy : (cc == 2 ? vz : 0.0));
+      }
+      // j-side: lane = j of the tile, every valid i of the wave (uniform
+      // index: scalar loads, four particles per batch; past nw the last
+      // particle repeats with zero mass)
+      const bool farw = __builtin_amdgcn_readfirstlane((int)far) != 0;
+      for (int p = 0; p < TJ / 64; ++p) {
+        const int k = 64 * p + l;
+        const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int q0 = 0; q0 < nw; q0 += 4) {
+          double qx[4], qy[4], qz[4], qm[4], qh[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int i = wbase + min(q0 + t, nw - 1);
+            qx[t] = X[i];
+            qy[t] = Y[i];
+            qz[t] = Z[i];
+            qm[t] = q0 + t < nw ? mass[i] : 0.0;
+            qh[t] = soft[i];
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const double dx = qx[t] - a.x, dy = qy[t] - a.y, dz = qz[t] - b.x;
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            double w = newton_w64<true>(r2, qm[t]);
+            if (!farw) {
+              const double h = c.x + qh[t];
+              if (r2 <= h * h) w = soft_w64(r2, h, qm[t]);
+            }
+            fx = fma(w, dx, fx);
+            fy = fma(w, dy, fy);
+            fz = fma(w, dz, fz);
+          }
+        }
+        jb[3 * k] = fx;
+        jb[3 * k + 1] = fy;
+        jb[3 * k + 2] = fz;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) two_sum_add(sum[r], cmp[r], part[r]);
+    // this thread's accumulator entry (j = jt + tid), read while the other
+    // waves finish
+    double acc6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (!first && jown) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc6[c] = jacc[(size_t)c * chunk + jl];
+    }
+    __syncthreads();
+
+    // tile's j-side: the four waves' sums in order, into the accumulator
+    if (jown) {
+      const int k = tid;
+      double f[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        f[c] = ((jbuf[3 * k + c] + jbuf[3 * (TJ + k) + c]) +
+                jbuf[3 * (2 * TJ + k) + c]) + jbuf[3 * (3 * TJ + k) + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (first) {
+          acc6[c] = f[c];
+          acc6[3 + c] = 0.0;
+        } else {
+          two_sum_add(acc6[c], acc6[3 + c], f[c]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) jacc[(size_t)c * chunk + jl] = acc6[c];
+    }
   }
 
 #pragma unroll
@@ -590,6 +913,74 @@ __global__ __launch_bounds__(kBlock) void k_force_f64_mfma(
                            gram, bmat);
 }
 
+// Symmetric FP64 kernel: block u is unit (R, s).  Units u < Q(Q-1)/2 are the
+// off-diagonal pairs in column order (u = s(s-1)/2 + R, R < s); the Q
+// diagonal units (lighter) come last.  iplane is [Q][3][n]; unit u < Q(Q-1)/2
+// owns jacc + u * 6C.
+template <int TJ>
+__global__ __launch_bounds__(kBlock, 3) void k_force_f64_sym(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ soft, int n, int chunk, int nchunks,
+    const double *__restrict__ tinfo, double *__restrict__ iplane,
+    double *__restrict__ jacc) {
+  __shared__ double2 tile[3 * TJ];
+  __shared__ double gram[4 * TJ];
+  __shared__ double bmat[4 * TJ];
+  __shared__ double jbuf[4 * TJ * 3];
+  const int nsym = nchunks * (nchunks - 1) / 2;
+  const int u = blockIdx.x;
+  int R, s;
+  if (u < nsym) {
+    s = (int)((1.0 + sqrt(1.0 + 8.0 * (double)u)) * 0.5);
+    while (s * (s - 1) / 2 > u) --s;
+    while ((s + 1) * s / 2 <= u) ++s;
+    R = u - s * (s - 1) / 2;
+  } else {
+    R = s = u - nsym;
+  }
+  const int ibeg = R * chunk, iend = min(n, ibeg + chunk);
+  const int jbeg = s * chunk, jend = min(n, jbeg + chunk);
+  double *out = iplane + (size_t)s * 3 * (size_t)n;
+  const double *ti = tinfo + (size_t)(jbeg / TJ) * 8;
+  if (R == s) {
+    for (int i0 = ibeg; i0 < iend; i0 += kBlock) {
+      force_block_f64_mfma<TJ>(pos, mass, soft, n, i0, iend, jbeg, jend, ti,
+                               out, tile, gram, bmat);
+    }
+    return;
+  }
+  double *ja = jacc + (size_t)u * 6 * (size_t)chunk;
+  for (int i0 = ibeg; i0 < iend; i0 += kBlock) {
+    sym_block_f64<TJ>(pos, mass, soft, n, i0, iend, jbeg, jend, ti, out, ja,
+                      chunk, i0 == ibeg, tile, gram, bmat, jbuf);
+  }
+}
+
+// acc[d][perm[p]] for p in chunk k: planes k .. Q-1 of iplane, then the
+// (value, error) accumulators of units (R, k), R < k, in that order,
+// compensated
+__global__ __launch_bounds__(kBlock) void k_reduce_sym(
+    const double *__restrict__ iplane, const double *__restrict__ jacc, int n,
+    int chunk, int nchunks, const int *__restrict__ perm,
+    double *__restrict__ acc) {
+  const size_t total = 3 * (size_t)n;
+  const size_t q = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= total) return;
+  const int d = (int)(q / n), p = (int)(q - (size_t)d * n);
+  const int k = p / chunk, loc = p - k * chunk;
+  double s = 0.0, c = 0.0;
+  for (int t = k; t < nchunks; ++t) {
+    two_sum_add(s, c, iplane[(size_t)t * total + (size_t)d * n + p]);
+  }
+  const size_t base = (size_t)k * (k - 1) / 2;
+  for (int R = 0; R < k; ++R) {
+    const double *ja = jacc + (base + R) * 6 * (size_t)chunk;
+    two_sum_add(s, c, ja[(size_t)d * chunk + loc]);
+    c += ja[(size_t)(3 + d) * chunk + loc];
+  }
+  acc[(size_t)d * n + perm[p]] = s + c;
+}
+
 template <int R, int TJ, bool KAHAN, bool CULL>
 __global__ __launch_bounds__(kBlock) void k_force_mixed(
     const float *__restrict__ shadow, int n, int jchunk,
@@ -696,6 +1087,24 @@ hipError_t launch_f64_mfma(const ForceLaunch &L, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Units of the symmetric kernel: Q chunks of jchunk particles (Q = jsplit)
+// must cover [0, n) with every chunk non-empty; checked here, before the
+// launch, since the kernel indexes iplane, jacc and tinfo by chunk.
+template <int TJ>
+hipError_t launch_f64_sym(const ForceLaunch &L, hipStream_t s) {
+  const int q = L.jsplit;
+  if (L.jchunk <= 0 || L.jchunk % TJ != 0 || q < 1 || q > 4096 ||
+      (long long)(q - 1) * L.jchunk >= L.n ||
+      (long long)q * L.jchunk < L.n || (q > 1 && !L.jacc) || !L.tinfo) {
+    return hipErrorInvalidValue;
+  }
+  const int units = q * (q + 1) / 2;
+  hipLaunchKernelGGL((k_force_f64_sym<TJ>), dim3(units), dim3(kBlock), 0, s,
+                     L.pos, L.mass, L.soft, L.n, L.jchunk, q, L.tinfo, L.out,
+                     L.jacc);
+  return hipGetLastError();
+}
+
 template <int R, int TJ, bool CULL>
 hipError_t launch_mixed(const ForceLaunch &L, hipStream_t s) {
   dim3 grid(ceil_div(L.n, (long long)kBlock * R), L.jsplit);
@@ -761,7 +1170,8 @@ hipError_t launch_batch_mixed(const BatchLaunch &L, hipStream_t s) {
 
 // variant bits: 1 = FP64 weight without the e^2 term; 2 = sorted input with
 // (wave, tile) culling of the softening test; 4 = matrix-core far field
-// (with 2: sorted input; a wave owns 64 particles, so it is listed as r = 1).
+// (with 2: sorted input; a wave owns 64 particles, so it is listed as r = 1);
+// 8 = symmetric units (with 2 and 4; jsplit is the chunk count).
 #define F64_SET(R)                                                  \
   {kClassF64, R, 128, 0, launch_f64<R, 128, true, false>},          \
       {kClassF64, R, 128, 1, launch_f64<R, 128, false, false>},     \
@@ -775,6 +1185,7 @@ const ForceVariant kVariants[] = {
     F64_SET(1),         F64_SET(2),         F64_SET(4),         F64_SET(8),
     {kClassF64, 1, 128, 6, launch_f64_mfma<128>},
     {kClassF64, 1, 256, 6, launch_f64_mfma<256>},
+    {kClassF64, 1, 256, 14, launch_f64_sym<256>},
     MIXED_SET(1, 128),  MIXED_SET(2, 256),  MIXED_SET(4, 256),  MIXED_SET(8, 256),
 };
 
@@ -804,6 +1215,20 @@ const ForceVariant *find_force_variant(int cls, int r, int tj, int variant) {
     }
   }
   return nullptr;
+}
+
+hipError_t launch_reduce_sym(const double *iplane, const double *jacc, int n,
+                             int chunk, int nchunks, const int *perm,
+                             double *acc, hipStream_t s) {
+  if (n <= 0 || chunk <= 0 || nchunks < 1 ||
+      (long long)(nchunks - 1) * chunk >= n ||
+      (long long)nchunks * chunk < n || (nchunks > 1 && !jacc)) {
+    return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(k_reduce_sym, dim3(ceil_div(3LL * n, kBlock)),
+                     dim3(kBlock), 0, s, iplane, jacc, n, chunk, nchunks, perm,
+                     acc);
+  return hipGetLastError();
 }
 
 const BatchVariant *batch_variants(int *count) {

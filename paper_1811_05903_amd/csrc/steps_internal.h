@@ -25,12 +25,14 @@ struct ForceLaunch {
   double *out = nullptr;       // [jsplit][3][n] (or acc when jsplit == 1)
   int kahan = 0;               // mixed only: Kahan FP32 accumulation
   const double *tinfo = nullptr;  // culled variants: [n/tj][8] tile boxes
+  double *jacc = nullptr;  // symmetric variant: [Q(Q-1)/2][6][jchunk]
 };
 
 // variant bits of a force kernel
 constexpr int kVarNoE2 = 1;  // FP64: r^-3 correction to first order only
 constexpr int kVarCull = 2;  // sorted input, (wave, tile) softening culling
 constexpr int kVarMfma = 4;  // FP64 far field on the matrix cores (with kVarCull)
+constexpr int kVarSym = 8;   // each pair once, both sides kept (with kVarMfma)
 
 struct ForceVariant {
   int cls;   // PrecClass
@@ -124,6 +126,12 @@ hipError_t launch_tile_info_f32(const float *shadow, int n, int tj,
 // acc[d][perm[k]] = sum over the jsplit partials [jsplit][3][n]
 hipError_t launch_reduce_scatter(const double *part, int jsplit, int n,
                                  const int *perm, double *acc, hipStream_t s);
+
+// Symmetric variant: acc[d][perm[p]] = planes k..Q-1 of iplane ([Q][3][n])
+// plus the accumulators of units (R, k), R < k, of jacc, k = p / chunk.
+hipError_t launch_reduce_sym(const double *iplane, const double *jacc, int n,
+                             int chunk, int nchunks, const int *perm,
+                             double *acc, hipStream_t s);
 
 // Sum jsplit partials [jsplit][3][n] into acc [3][n] in fixed order.
 hipError_t launch_reduce_partials(const double *part, int jsplit, int n,

@@ -72,7 +72,7 @@ def _variants(st):
         ctx = st.Context(0, precision=prec)
         for r in (1, 2, 4, 8):
             for tj in (128, 256):
-                for var in (0, 1, 2, 3, 6):
+                for var in (0, 1, 2, 3, 6, 14):
                     for js in (1, 3, 7):
                         try:
                             ctx.set_tile(r, tj, js, var)
@@ -88,9 +88,10 @@ def test_every_launch_shape(st):
     pos, mass, soft = clustered(1537, 23, 0.1)
     ref = oracle.forces(pos, mass, soft)
     shapes = _variants(st)
-    # FP64: 4 r x 4 variants + two matrix-core tiles; mixed, Kahan: 4 r x 2
-    # variants; 3 splits each
-    assert len(shapes) == (18 + 8 + 8) * 3
+    # FP64: 4 r x 4 variants + two matrix-core tiles + the symmetric one;
+    # mixed, Kahan: 4 r x 2 variants; 3 splits each (for the symmetric
+    # kernel 1, 3 and 7 chunks, the last one a single particle)
+    assert len(shapes) == (19 + 8 + 8) * 3
     ctxs = {p: st.Context(0, precision=p) for p in ("fp64", "mixed", "kahan")}
     for prec, r, tj, var, js in shapes:
         ctx = ctxs[prec]
@@ -148,6 +149,45 @@ def test_matrix_core_kernel_parity(st, n, tj):
         np.random.default_rng(4).choice(ps.n, 256, replace=False)
     err = rel_err(got[:, idx], oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx))
     _report("fp64 matrix-core tj=%d n=%d" % (tj, ps.n), err)
+    assert err.max() <= FP64_TOL
+
+
+@pytest.mark.parametrize("q", [2, 3, 8, 0])
+@pytest.mark.parametrize("kind", ["stereo", "clustered"])
+def test_symmetric_kernel_parity(st, kind, q):
+    # variant 14: each pair between two chunks evaluated once and applied to
+    # both particles.  Ragged n; q chunks (0: the built-in count); the
+    # clustered set puts near and softened blocks between chunks (the direct
+    # loop of the j-side), the stereographic one mostly matrix-core blocks
+    if kind == "stereo":
+        ps = synth.config(2, n=20001)
+        pos, mass, soft = ps.pos, ps.mass, ps.soft
+    else:
+        pos, mass, soft = clustered(9000, 37, 0.1)
+    ctx = st.Context(0, precision="fp64")
+    ctx.set_tile(1, 256, q, 14)
+    got = _gpu_forces(st, pos, mass, soft, ctx)
+    again = _gpu_forces(st, pos, mass, soft, ctx)
+    tile = ctx.get_tile(mass.size)
+    ctx.close()
+    assert np.array_equal(got, again)
+    assert tile["variant"] == 14 and tile["jsplit"] >= 1
+    err = rel_err(got, oracle.forces(pos, mass, soft))
+    _report("fp64 symmetric %s q=%d (jsplit %d)" % (kind, q, tile["jsplit"]), err)
+    assert np.all(np.isfinite(got))
+    assert err.max() <= FP64_TOL
+
+
+def test_symmetric_kernel_full_size_sampled(st):
+    # N = 2^18 with the built-in chunk count; oracle on 256 sampled rows
+    ps = synth.config(2)
+    ctx = st.Context(0, precision="fp64")
+    ctx.set_tile(1, 256, 0, 14)
+    got = _gpu_forces(st, ps.pos, ps.mass, ps.soft, ctx)
+    ctx.close()
+    idx = np.random.default_rng(5).choice(ps.n, 256, replace=False)
+    err = rel_err(got[:, idx], oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx))
+    _report("fp64 symmetric config2 sampled", err)
     assert err.max() <= FP64_TOL
 
 
