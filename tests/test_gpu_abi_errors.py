@@ -118,9 +118,14 @@ def test_step_overlapping_state_rejected(st):
 
 def test_bad_tile_rejected(st):
     ctx = st.Context(0)
-    for args in ((3, 128, 1, 0), (4, 64, 1, 0), (4, 128, 0, 0), (4, 128, 1, 5)):
+    for args in ((3, 128, 1, 0), (4, 64, 1, 0), (4, 128, -1, 0),
+                 (4, 128, 1025, 0), (4, 128, 1, 5), (1, 128, 1, 14)):
         with pytest.raises(st.StepsError):
             ctx.set_tile(*args)
+    # jsplit 0: the forced kernel with the built-in split for each n
+    ctx.set_tile(1, 256, 0, 14)
+    t = ctx.get_tile(262144)
+    assert t["variant"] == 14 and t["jsplit"] > 1
     ctx.set_precision("mixed")
     with pytest.raises(st.StepsError):
         ctx.set_tile(4, 128, 1, 1)   # FP64-only variant
