@@ -132,6 +132,22 @@ def test_autotune_picks_a_compiled_shape_and_keeps_parity(st, prec, tmp_path):
         assert np.median(err) <= 1e-5
 
 
+def test_autotune_full_size_includes_symmetric(st, tmp_path):
+    # at N = 2^18 the candidates include the symmetric kernel (variant 14,
+    # chunk counts Q/2 and Q); the tuned shape keeps parity on sampled rows
+    ps = synth.config(2)
+    ctx = st.Context(0, precision="fp64")
+    p, m, h = dev(ps.pos), dev(ps.mass), dev(ps.soft)
+    tile = st.steps_autotune(p, m, h, ctx, cache=str(tmp_path / "t.json"))
+    print("tuned at 2^18:", tile, flush=True)
+    assert tile["variant"] in (0, 3, 6, 14)
+    got = host(st.steps_forces(p, m, h, ctx=ctx))
+    ctx.close()
+    idx = np.random.default_rng(11).choice(ps.n, 128, replace=False)
+    err = rel_err(got[:, idx], oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx))
+    assert err.max() <= FP64_TOL
+
+
 @pytest.mark.parametrize("tj", [128, 256])
 @pytest.mark.parametrize("n", [40000, None])
 def test_matrix_core_kernel_parity(st, n, tj):
@@ -175,6 +191,22 @@ def test_symmetric_kernel_parity(st, kind, q):
     err = rel_err(got, oracle.forces(pos, mass, soft))
     _report("fp64 symmetric %s q=%d (jsplit %d)" % (kind, q, tile["jsplit"]), err)
     assert np.all(np.isfinite(got))
+    assert err.max() <= FP64_TOL
+
+
+def test_symmetric_kernel_ragged_default_shape(st):
+    # N = 2^18 + 37 in the default shape (the symmetric kernel with a ragged
+    # last chunk and a partial last tile); the last 40 rows and 88 others
+    n = 262144 + 37
+    ps = synth.config(2, n=n)
+    ctx = st.Context(0, precision="fp64")
+    assert ctx.get_tile(n)["variant"] == 14
+    got = _gpu_forces(st, ps.pos, ps.mass, ps.soft, ctx)
+    ctx.close()
+    rng = np.random.default_rng(6)
+    idx = np.concatenate([np.arange(n - 40, n), rng.choice(n - 40, 88, replace=False)])
+    err = rel_err(got[:, idx], oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx))
+    _report("fp64 symmetric ragged n=%d" % n, err)
     assert err.max() <= FP64_TOL
 
 
