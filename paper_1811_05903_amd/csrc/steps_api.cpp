@@ -30,6 +30,9 @@ constexpr int64_t kMaxN = int64_t(1) << 30;
 constexpr int64_t kSortMinN = 32768;
 constexpr int64_t kMfmaMinN = 131072;
 constexpr int64_t kSymMinN = 262144;
+// below this many chunks (the memory cap binds from N ~ 2^22.5) the units
+// no longer fill the device evenly and the one-sided kernel is used
+constexpr int kSymMinChunks = 64;
 
 thread_local std::string t_err;
 
@@ -219,7 +222,8 @@ int heuristic_jsplit(int cls, int64_t n, int r, int tj, int variant) {
 // Launch shape: a forced tile, else a shape tuned for (class, n), else the
 // heuristic, measured on MI355X at N = 2^15 ... 2^21:
 //   * FP64 from kSymMinN up: the symmetric matrix-core kernel (variant 14),
-//     7% ahead of the one-sided one at 2^18 and 17% at 2^20 and 2^21;
+//     15% ahead of the one-sided one at 2^18 and 23-25% at 2^20 and 2^21,
+//     while its memory cap still allows kSymMinChunks chunks;
 //   * FP64 from kMfmaMinN up: the matrix-core kernel (variant 6, tj 256),
 //     5-7% ahead of the VALU kernel there and 7% behind it at 2^15;
 //   * otherwise FP64 r = 4, mixed r = 2 (fewer registers, more waves to pair
@@ -245,7 +249,9 @@ steps_tile choose_tile(const steps_ctx *c, int64_t n) {
     t.r = 1;
     t.tj = 256;
     t.variant = steps::kVarCull | steps::kVarMfma;
-    if (n >= kSymMinN) t.variant |= steps::kVarSym;
+    if (n >= kSymMinN && sym_chunks(n) >= kSymMinChunks) {
+      t.variant |= steps::kVarSym;
+    }
   } else {
     int r = f64 ? 4 : 2;
     while (r > 1 && (n + 256LL * r - 1) / (256LL * r) < 256) r /= 2;
