@@ -8,7 +8,9 @@
 //     i = start + 64*r + l for r < R in registers (coalesced loads/stores);
 //   * grid.y splits the j range into jsplit chunks (multiples of TJ); each
 //     chunk streams through LDS in tiles of TJ particles, staged with
-//     coalesced SoA reads and read back by every lane as broadcasts;
+//     coalesced SoA reads and read back by every lane as broadcasts (the
+//     symmetric kernel instead runs a 1-D grid of chunk pairs, each pair
+//     evaluated once for both particles);
 //   * a lane sums a tile's terms into a per-tile partial and adds it to its
 //     running total after the tile (blocked summation: rounding grows with
 //     TJ + N/TJ rather than N; in FP64 the running total is also
