@@ -51,7 +51,10 @@ extern "C" {
 /* ---- return codes ----------------------------------------------------- */
 #define STEPS_OK 0
 #define STEPS_E_INVAL (-1)       /* bad argument (null pointer, n < 0, ...) */
-#define STEPS_E_NOMEM (-2)       /* device scratch allocation failed */
+#define STEPS_E_NOMEM (-2)       /* device scratch allocation failed (an
+                                    automatically chosen symmetric shape
+                                    first falls back to the one-sided
+                                    kernel, which needs far less) */
 #define STEPS_E_HIP (-3)         /* HIP runtime error; message has the text */
 #define STEPS_E_NONFINITE (-4)   /* non-finite input (STEPS_CHECK_FINITE) */
 #define STEPS_E_UNSUPPORTED (-5) /* option not supported by this mode/call */

@@ -347,14 +347,12 @@ int run_forces_periodic(steps_ctx *c, const double *pos, const double *mass,
   return STEPS_OK;
 }
 
-int run_forces(steps_ctx *c, const double *pos, const double *mass,
-               const double *soft, int n, double *acc) {
-  if (n == 0) return STEPS_OK;
-  if (c->images != STEPS_IMAGES_NONE) {
-    return run_forces_periodic(c, pos, mass, soft, n, acc);
-  }
+// One force evaluation in launch shape t.  Scratch is allocated before
+// anything is enqueued, so an STEPS_E_NOMEM return has enqueued nothing.
+int run_forces_tile(steps_ctx *c, const double *pos, const double *mass,
+                    const double *soft, int n, double *acc,
+                    const steps_tile &t) {
   const int cls = prec_class(c->precision);
-  const steps_tile t = choose_tile(c, n);
   const steps::ForceVariant *v =
       steps::find_force_variant(cls, t.r, t.tj, t.variant);
   if (!v) {
@@ -470,6 +468,26 @@ int run_forces(steps_ctx *c, const double *pos, const double *mass,
     if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
   }
   return STEPS_OK;
+}
+
+int run_forces(steps_ctx *c, const double *pos, const double *mass,
+               const double *soft, int n, double *acc) {
+  if (n == 0) return STEPS_OK;
+  if (c->images != STEPS_IMAGES_NONE) {
+    return run_forces_periodic(c, pos, mass, soft, n, acc);
+  }
+  const steps_tile t = choose_tile(c, n);
+  int rc = run_forces_tile(c, pos, mass, soft, n, acc, t);
+  if (rc == STEPS_E_NOMEM && (t.variant & steps::kVarSym) && !c->tile_forced) {
+    // the symmetric kernel's partial sums (about 48 Q n bytes) did not fit:
+    // the one-sided matrix-core kernel needs far less
+    steps_tile u = t;
+    u.variant &= ~steps::kVarSym;
+    u.jsplit = heuristic_jsplit(prec_class(c->precision), n, u.r, u.tj,
+                                u.variant);
+    rc = run_forces_tile(c, pos, mass, soft, n, acc, u);
+  }
+  return rc;
 }
 
 // Enqueue phi <- G-free softened potential (FP64, unsorted kernel r=2,

@@ -8,8 +8,9 @@ import math
 import numpy as np
 import pytest
 
+import oracle
 import synth
-from gpu_util import dev, host
+from gpu_util import dev, host, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -208,3 +209,38 @@ def test_impossible_scratch_allocation_is_reported(st):
     got = st.steps_forces(dev(ps.pos), dev(ps.mass), dev(ps.soft), ctx=ctx)
     assert bool(torch.isfinite(got).all())
     ctx.close()
+
+
+def test_symmetric_shape_falls_back_when_scratch_is_short(st):
+    # N = 2^18: the automatic shape is the symmetric kernel, whose partial
+    # sums take ~2 GB.  With all but ~700 MB of device memory held, that
+    # allocation fails before any launch and the call runs the one-sided
+    # matrix-core kernel (~0.43 GB of scratch) instead, to the same bar
+    import torch
+    ps = synth.config(2)
+    p, m, h = dev(ps.pos), dev(ps.mass), dev(ps.soft)
+    acc = torch.zeros_like(p)
+    ctx = st.Context(0, precision="fp64")
+    assert ctx.get_tile(ps.n)["variant"] == 14
+    torch.cuda.synchronize()
+    free, _ = torch.cuda.mem_get_info()
+    try:
+        hold = torch.empty(free - (700 << 20), dtype=torch.uint8, device="cuda")
+    except RuntimeError:
+        pytest.skip("could not hold the device memory")
+    try:
+        # less than the symmetric partials need (24 n Q + 48 C Q (Q - 1) / 2
+        # bytes, Q = 171 chunks of C = 1536: 2.15 GB) is left, and more than
+        # the one-sided kernel needs
+        left = torch.cuda.mem_get_info()[0]
+        assert (500 << 20) < left < 1.9e9, left
+        st.steps_forces(p, m, h, acc=acc, ctx=ctx)
+        torch.cuda.synchronize()
+    finally:
+        del hold
+        torch.cuda.empty_cache()
+    ctx.close()
+    idx = np.random.default_rng(8).choice(ps.n, 64, replace=False)
+    ref = oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx)
+    assert rel_err(host(acc)[:, idx], ref).max() <= 1e-12
+
