@@ -13,12 +13,17 @@ interactions per second over the timed steps (N^2 per step).
 Also reported on the same JSON line:
   roofline     -- force kernel: 20 flop per ordered pair (convention) over
                   its average launch time (HIP events on its own stream),
-                  against the FP64 vector peak 78.6 TFLOP/s ("bound": "alu");
+                  against the FP64 peak 78.6 TFLOP/s ("bound": "mfma" for the
+                  matrix-core kernels, which share that pipe, else "alu");
   cpu_baseline -- the CPU FP64 oracle on a bounded seeded sample of i rows
                   against all N j (rank 0 only);
   modes        -- force-kernel pair rate in FP64 and both mixed modes at the
                   same N and at N = 2^21, with the relative force error
                   against the oracle sample (median, max).
+
+--workload 3 runs the three precision modes at N = 2^21 against the oracle
+on 65 536 sampled rows (about a minute of host time); --workload 5 runs
+N = 2^22 for 50 steps in mixed precision and in FP64 with the energy checks.
 """
 from __future__ import annotations
 
@@ -89,6 +94,9 @@ def main():
 
     if args.workload == 5:
         print(json.dumps(workload5(st, dev, args)), flush=True)
+        return
+    if args.workload == 3:
+        print(json.dumps(workload3(st, dev, args)), flush=True)
         return
 
     ps = synth.config(args.workload)
@@ -583,6 +591,51 @@ def binned_errors(err, kappa, radius, nbins=3):
                          "max": float(err[part].max()), "rows": int(part.size)})
         out[name] = bins
     return out
+
+
+def workload3(st, dev, args, rows=65536):
+    """Workload 3: N = 2^21, one force evaluation per precision mode (FP64,
+    FP32 pairs with FP64 accumulation, FP32 pairs with Kahan accumulation),
+    each against the FP64 oracle on `rows` seeded-sampled i (all j), with
+    pair-interactions/s and the mixed-to-FP64 ratio."""
+    import numpy as np
+    import oracle
+    import synth
+    ps = synth.config(3)
+    n = ps.n
+    log("workload 3: n=%d, oracle on %d sampled rows (%d threads)"
+        % (n, rows, oracle.num_threads()))
+    idx = np.sort(np.random.default_rng(33).choice(n, rows, replace=False))
+    refs, kaps = [], []
+    t0 = time.perf_counter()
+    step = 8192
+    for k in range(0, rows, step):
+        r, kp = oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx[k:k + step],
+                              want_kappa=True)
+        refs.append(r)
+        kaps.append(kp)
+        log("oracle rows %d/%d (%.0f s)" % (min(rows, k + step), rows,
+                                            time.perf_counter() - t0))
+    odt = time.perf_counter() - t0
+    sample = (idx, np.concatenate(refs, axis=1), np.concatenate(kaps))
+    modes = mode_table(st, ps, sample, dev)
+    return {
+        "metric": "pair interactions/s (ordered pairs, one force evaluation)",
+        "value": modes["fp64"]["pairs_per_s"],
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "data": "synthetic",
+        "config": {"workload": "stereographic sphere N=%d D=%g r_max=%g, "
+                               "three precision modes" % (n, ps.params["D"],
+                                                          ps.params["r_max"]),
+                   "n": n, "parallelism": "single GPU"},
+        "modes": modes,
+        "cpu_baseline": {"value": float(rows) * n / odt, "unit": "pairs/s",
+                         "cores": oracle.num_threads(), "kind": "oracle",
+                         "sample": "FP64 oracle pair sums for %d seeded-sampled "
+                                   "i against all %d j (%.1f s)" % (rows, n, odt)},
+    }
 
 
 def mode_table(st, ps, rows, dev):
