@@ -168,6 +168,51 @@ def test_layzer_irvine_through_gpu_path(st):
     assert np.abs(R).max() < 5e-2 * scale
 
 
+def test_config2_subset_energy_and_momentum_200_steps(st):
+    # the 4096-particle member of workload 2 (same recipe) over its 200 log
+    # steps a 0.02 -> 1.0, on the GPU and in the oracle (both FP64).  The two
+    # runs start 1e-15 apart and the collapse amplifies that about 1e3-fold
+    # per 25 steps from step 50 (measured: residual curves 2.6e-14 apart at
+    # step 50, 5.9e-12 at 75, 1.8e-3 at 150; positions a median 220 h apart
+    # at a = 1).  So the Layzer-Irvine residual curves must agree closely
+    # over the first 75 steps, the final residuals (the integrator's error,
+    # ~2e-2 of max |W|) within a factor of two, and the peculiar momentum,
+    # which the pair sum conserves, to rounding
+    ps = synth.config(2, n=4096)
+    grid = ps.a_grid()
+    nst = len(grid) - 1
+    oc, gc = _pair(st, ps.cosmo)
+    p, v, m, h = dev(ps.pos), dev(ps.vel), dev(ps.mass), dev(ps.soft)
+    acc = st.steps_forces(p, m, h)
+    es = [st.steps_energy(p, v, m, h, grid[0], gc)]
+    for k in range(nst):
+        st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], gc)
+        es.append(st.steps_energy(p, v, m, h, grid[k + 1], gc))
+    R = oracle.layzer_irvine(es, grid, oc)
+    po, vo = ps.pos.copy(), ps.vel.copy()
+    So = oracle.forces(po, ps.mass, ps.soft)
+    eo = [oracle.energy(po, vo, ps.mass, ps.soft, grid[0], oc)]
+    for k in range(nst):
+        oracle.kdk_step(po, vo, ps.mass, ps.soft, So, grid[k], grid[k + 1] - grid[k], oc)
+        eo.append(oracle.energy(po, vo, ps.mass, ps.soft, grid[k + 1], oc))
+    Ro = oracle.layzer_irvine(eo, grid, oc)
+    scale = max(abs(e["W"]) for e in eo)
+    dR = np.abs(R - Ro) / scale
+    dx = np.linalg.norm(host(p) - po, axis=0) / ps.soft
+    P, Po = np.asarray(es[-1]["P"]), np.asarray(eo[-1]["P"])
+    pscale = float(np.sum(ps.mass * np.linalg.norm(vo, axis=0)))
+    dP = np.abs(P - Po).max() / pscale
+    print("config2 subset, %d steps: |R|/max|W| gpu %.3e oracle %.3e; "
+          "curve diff max %.2e (step 50: %.2e); |dP|/sum m|v| %.2e; "
+          "|dx|/h median %.2e max %.2e" % (
+              nst, abs(R[-1]) / scale, abs(Ro[-1]) / scale, dR.max(), dR[50],
+              dP, np.median(dx), dx.max()), flush=True)
+    print("curve diff every 25 steps:", " ".join("%.1e" % dR[k] for k in range(0, nst + 1, 25)), flush=True)
+    assert dR[:76].max() < 1e-10
+    assert 0.5 < abs(R[-1]) / abs(Ro[-1]) < 2.0
+    assert dP < 1e-12
+
+
 @pytest.mark.parametrize("prec", ["mixed", "kahan"])
 def test_mixed_step_close_to_fp64(st, prec):
     ps = synth.config(1, n=2048)
