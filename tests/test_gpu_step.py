@@ -35,7 +35,7 @@ def _pair(st, c, newtonian=False, G=None):
     return o, g
 
 
-@pytest.mark.parametrize("n,steps", [(1024, 100), (4096, 10)])
+@pytest.mark.parametrize("n,steps", [(1024, 100), (4096, 100)])
 def test_config1_trajectory_parity(st, n, steps):
     ps = synth.config(1, n=n)
     grid = ps.a_grid()[: steps + 1]
