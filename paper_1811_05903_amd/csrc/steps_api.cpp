@@ -309,9 +309,79 @@ struct Carve {
   }
 };
 
+// Morton order for the culled kernels: bbox -> keys -> stable sort ->
+// sorted copy (FP64 [5][n], or the FP32 shadow in mixed mode) -> boxes of
+// tiles of tj particles, all in the context arena, with extra_bytes more
+// carved after them.  Allocation comes first, so an error return has
+// enqueued nothing.
+struct SortedState {
+  const int *perm = nullptr;  // sorted position -> caller index
+  double *sorted = nullptr;   // FP64 x, y, z, m, h (kClassF64)
+  float *shadow = nullptr;    // FP32 x, y, z, m, h (kClassMixed)
+  double *info = nullptr;     // [ntiles][8] tile boxes
+  char *extra = nullptr;
+};
+
+int sort_for_culling(steps_ctx *c, const double *pos, const double *mass,
+                     const double *soft, int n, int tj, int cls,
+                     size_t extra_bytes, SortedState *S) {
+  size_t cub_bytes = 0;
+  hipError_t e = steps::sort_pairs(nullptr, &cub_bytes, nullptr, nullptr,
+                                   nullptr, nullptr, n, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "radix sort size query");
+  const int ntiles = (n + tj - 1) / tj;
+  Carve cv;
+  const size_t o_box = cv.take(6 * sizeof(double));
+  const size_t o_bpart = cv.take((size_t)steps::bbox_blocks(n) * 6 * sizeof(double));
+  const size_t o_k0 = cv.take((size_t)n * 8), o_k1 = cv.take((size_t)n * 8);
+  const size_t o_v0 = cv.take((size_t)n * 4), o_v1 = cv.take((size_t)n * 4);
+  const size_t o_cub = cv.take(cub_bytes);
+  const size_t o_info = cv.take((size_t)ntiles * 8 * sizeof(double));
+  const size_t o_soa = cv.take(cls == steps::kClassF64
+                                   ? 5 * (size_t)n * sizeof(double)
+                                   : 5 * (size_t)n * sizeof(float));
+  const size_t o_extra = cv.take(extra_bytes);
+  int rc = ensure(c, c->arena, cv.off, "sort");
+  if (rc) return rc;
+  char *base = (char *)c->arena.p;
+  double *box = (double *)(base + o_box);
+  auto *k0 = (unsigned long long *)(base + o_k0);
+  auto *k1 = (unsigned long long *)(base + o_k1);
+  int *v0 = (int *)(base + o_v0), *v1 = (int *)(base + o_v1);
+  S->info = (double *)(base + o_info);
+  S->extra = extra_bytes ? base + o_extra : nullptr;
+  if ((e = steps::launch_bbox(pos, n, (double *)(base + o_bpart), box,
+                              c->stream)) != hipSuccess ||
+      (e = steps::launch_morton(pos, n, box, k0, v0, c->stream)) !=
+          hipSuccess) {
+    return hip_fail(e, "sort-key kernel launch");
+  }
+  e = steps::sort_pairs(base + o_cub, &cub_bytes, k0, k1, v0, v1, n,
+                        c->stream);
+  if (e != hipSuccess) return hip_fail(e, "radix sort");
+  S->perm = v1;
+  if (cls == steps::kClassF64) {
+    S->sorted = (double *)(base + o_soa);
+    e = steps::launch_gather(pos, mass, soft, v1, n, S->sorted, nullptr,
+                             c->stream);
+    if (e == hipSuccess) {
+      e = steps::launch_tile_info_f64(S->sorted, n, tj, S->info, c->stream);
+    }
+  } else {
+    S->shadow = (float *)(base + o_soa);
+    e = steps::launch_gather(pos, mass, soft, v1, n, nullptr, S->shadow,
+                             c->stream);
+    if (e == hipSuccess) {
+      e = steps::launch_tile_info_f32(S->shadow, n, tj, S->info, c->stream);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(e, "gather kernel launch");
+  return STEPS_OK;
+}
+
 // Enqueue acc <- S(pos) in the context's precision.  Arguments validated.
-// Periodic pair sum: FP64 kernel over unsorted particles, j-split
-// partials reduced in fixed order.
+// Periodic pair sum: FP64 kernel over Morton-sorted particles, j-split
+// partials reduced in fixed order and scattered to the caller's order.
 int run_forces_periodic(steps_ctx *c, const double *pos, const double *mass,
                         const double *soft, int n, double *acc) {
   if (c->precision != STEPS_FP64) {
@@ -319,31 +389,30 @@ int run_forces_periodic(steps_ctx *c, const double *pos, const double *mass,
                 "periodic boxes are computed in FP64 only");
   }
   const int tj = steps::periodic_tile();
-  const int64_t nb = steps::periodic_iblocks(n);
-  int64_t want = (8192 + nb - 1) / nb;
+  const int64_t nb = steps::periodic_iblocks(n);  // one-wave workgroups
+  int64_t want = (32768 + nb - 1) / nb;
   want = std::min<int64_t>(want, std::max<int64_t>(1, n / (2LL * tj)));
   int chunk = 0, js = 1;
   split_j(n, tj, (int)std::max<int64_t>(1, std::min<int64_t>(want, 1024)),
           &chunk, &js);
-  double *out = acc;
-  int rc;
-  if (js > 1) {
-    rc = ensure(c, c->part, (size_t)js * 3 * (size_t)n * sizeof(double),
-                "partial-sum");
-    if (rc) return rc;
-    out = (double *)c->part.p;
+  int rc = ensure(c, c->part, (size_t)js * 3 * (size_t)n * sizeof(double),
+                  "partial-sum");
+  if (rc) return rc;
+  double *out = (double *)c->part.p;
+  SortedState S;
+  if ((rc = sort_for_culling(c, pos, mass, soft, n, tj, steps::kClassF64, 0,
+                             &S))) {
+    return rc;
   }
   hipEvent_t ev[2] = {nullptr, nullptr};
   if ((rc = prof_begin(c, ev))) return rc;
-  hipError_t e = steps::launch_force_periodic(pos, mass, soft, n, c->box_L,
-                                              c->images, chunk, js, out,
-                                              c->stream);
+  hipError_t e = steps::launch_force_periodic(
+      S.sorted, S.sorted + 3 * (size_t)n, S.sorted + 4 * (size_t)n, n,
+      c->box_L, c->images, chunk, js, S.info, out, c->stream);
   if (e != hipSuccess) return hip_fail(e, "periodic force kernel launch");
   if ((rc = prof_end(c, ev))) return rc;
-  if (js > 1) {
-    e = steps::launch_reduce_partials(out, js, n, acc, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "partial reduction launch");
-  }
+  e = steps::launch_reduce_scatter(out, js, n, S.perm, acc, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "partial reduction launch");
   return STEPS_OK;
 }
 
@@ -380,65 +449,25 @@ int run_forces_tile(steps_ctx *c, const double *pos, const double *mass,
   }
   const int *perm = nullptr;
   if (cull) {
-    // Morton order: bbox -> keys -> stable sort -> sorted copy -> tile boxes
-    size_t cub_bytes = 0;
-    e = steps::sort_pairs(nullptr, &cub_bytes, nullptr, nullptr, nullptr,
-                          nullptr, n, c->stream);
-    if (e != hipSuccess) return hip_fail(e, "radix sort size query");
-    const int ntiles = (n + t.tj - 1) / t.tj;
-    Carve cv;
-    const size_t o_box = cv.take(6 * sizeof(double));
-    const size_t o_bpart = cv.take((size_t)steps::bbox_blocks(n) * 6 * sizeof(double));
-    const size_t o_k0 = cv.take((size_t)n * 8), o_k1 = cv.take((size_t)n * 8);
-    const size_t o_v0 = cv.take((size_t)n * 4), o_v1 = cv.take((size_t)n * 4);
-    const size_t o_cub = cv.take(cub_bytes);
-    const size_t o_info = cv.take((size_t)ntiles * 8 * sizeof(double));
-    const size_t o_soa = cv.take(cls == steps::kClassF64
-                                     ? 5 * (size_t)n * sizeof(double)
-                                     : 5 * (size_t)n * sizeof(float));
     // symmetric variant: one (value, error) accumulator per off-diagonal unit
-    const size_t o_jacc = cv.take(
+    const size_t jacc_bytes =
         sym ? (size_t)js * (js - 1) / 2 * 6 * (size_t)chunk * sizeof(double)
-            : 0);
-    if ((rc = ensure(c, c->arena, cv.off, "sort"))) return rc;
-    char *base = (char *)c->arena.p;
-    double *box = (double *)(base + o_box);
-    auto *k0 = (unsigned long long *)(base + o_k0);
-    auto *k1 = (unsigned long long *)(base + o_k1);
-    int *v0 = (int *)(base + o_v0), *v1 = (int *)(base + o_v1);
-    double *info = (double *)(base + o_info);
-    if ((e = steps::launch_bbox(pos, n, (double *)(base + o_bpart), box,
-                                c->stream)) != hipSuccess ||
-        (e = steps::launch_morton(pos, n, box, k0, v0, c->stream)) !=
-            hipSuccess) {
-      return hip_fail(e, "sort-key kernel launch");
+            : 0;
+    SortedState S;
+    if ((rc = sort_for_culling(c, pos, mass, soft, n, t.tj, cls, jacc_bytes,
+                               &S))) {
+      return rc;
     }
-    e = steps::sort_pairs(base + o_cub, &cub_bytes, k0, k1, v0, v1, n,
-                          c->stream);
-    if (e != hipSuccess) return hip_fail(e, "radix sort");
-    perm = v1;
+    perm = S.perm;
     if (cls == steps::kClassF64) {
-      double *sorted = (double *)(base + o_soa);
-      e = steps::launch_gather(pos, mass, soft, perm, n, sorted, nullptr,
-                               c->stream);
-      if (e == hipSuccess) {
-        e = steps::launch_tile_info_f64(sorted, n, t.tj, info, c->stream);
-      }
-      L.pos = sorted;
-      L.mass = sorted + 3 * (size_t)n;
-      L.soft = sorted + 4 * (size_t)n;
+      L.pos = S.sorted;
+      L.mass = S.sorted + 3 * (size_t)n;
+      L.soft = S.sorted + 4 * (size_t)n;
     } else {
-      float *shadow = (float *)(base + o_soa);
-      e = steps::launch_gather(pos, mass, soft, perm, n, nullptr, shadow,
-                               c->stream);
-      if (e == hipSuccess) {
-        e = steps::launch_tile_info_f32(shadow, n, t.tj, info, c->stream);
-      }
-      L.shadow = shadow;
+      L.shadow = S.shadow;
     }
-    if (e != hipSuccess) return hip_fail(e, "gather kernel launch");
-    L.tinfo = info;
-    if (sym && js > 1) L.jacc = (double *)(base + o_jacc);
+    L.tinfo = S.info;
+    if (sym && js > 1) L.jacc = (double *)S.extra;
   } else if (cls == steps::kClassMixed) {
     rc = ensure(c, c->shadow, 5 * (size_t)n * sizeof(float), "FP32 shadow");
     if (rc) return rc;

@@ -150,10 +150,13 @@ hipError_t launch_reduce_partials1(const double *part, int jsplit, int n,
 // image within 2.6 L; out as the force kernels ([jsplit][3][n] partials)
 int periodic_tile();
 int periodic_iblocks(int n);
+// over Morton-sorted particles with the boxes of their tiles of
+// periodic_tile() particles in tinfo
 hipError_t launch_force_periodic(const double *pos, const double *mass,
                                  const double *soft, int n, double L,
                                  int images, int jchunk, int jsplit,
-                                 double *out, hipStream_t s);
+                                 const double *tinfo, double *out,
+                                 hipStream_t s);
 // adaptive step: out[0] <- min_i 2.8 h_i / |g S_i + rad x_i - drag v_i|
 int dt_blocks(int n);
 hipError_t launch_dt_min(const double *pos, const double *vel,
