@@ -174,7 +174,8 @@ def main():
                      "flop_per_pair": FLOP_PER_PAIR},
     }
 
-    sample_rows = None
+    sample_rows = big_rows = None
+    big = None if args.no_modes else synth.config(3)
     if not args.no_cpu_baseline:
         import oracle
         rng = np.random.default_rng(12345)
@@ -196,16 +197,15 @@ def main():
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "FP64 oracle pair sums for %d seeded-sampled i of the "
                       "N=%d set against all j (%.1f s)" % (m, n, dt)}
-
-    if not args.no_modes:
-        out["modes"] = mode_table(st, ps, sample_rows, dev)
-        big = synth.config(3)
-        big_rows = None
-        if not args.no_cpu_baseline:
-            import oracle
+        if not args.no_modes:
+            # the oracle's rows of the 2^21 set, the reference of its modes
+            # table (not part of the timed sample above)
             bidx = np.sort(np.random.default_rng(3).choice(big.n, 32, replace=False))
             big_rows = (bidx,) + oracle.forces(big.pos, big.mass, big.soft, idx=bidx,
                                                want_kappa=True)
+
+    if not args.no_modes:
+        out["modes"] = mode_table(st, ps, sample_rows, dev)
         out["modes_n2e21"] = mode_table(st, big, big_rows, dev)
     if not args.no_batch:
         out["batch"] = batch_leg(st, dev, args.batch_steps)

@@ -150,7 +150,9 @@ int steps_ctx_create(int device, steps_ctx **out);
  * no-op. */
 int steps_ctx_destroy(steps_ctx *ctx);
 /* Enqueue subsequent work on `stream` (a hipStream_t on the context's
- * device; NULL = the null stream).  The caller keeps the stream alive. */
+ * device; NULL = the null stream).  The caller keeps the stream alive.
+ * Switching to another stream first waits for the work already enqueued on
+ * the old one, whose scratch the new stream's work may reuse. */
 int steps_ctx_set_stream(steps_ctx *ctx, void *stream);
 int steps_ctx_set_precision(steps_ctx *ctx, int precision);
 int steps_ctx_set_flags(steps_ctx *ctx, uint32_t flags);
@@ -198,7 +200,9 @@ int steps_ctx_force_timing(steps_ctx *ctx, double *total_ms, int64_t *count,
 /* acc <- S (G-free pair sum, see top of file) for all n particles.
  * pos [3][n], mass [n], soft [n] (softening lengths h_i >= 0, the support
  * radius of particle i's share of the kernel), acc [3][n] output.
- * n == 0 is a no-op; n == 1 gives acc = 0.  n must be <= 2^30. */
+ * n == 0 is a no-op; n == 1 gives acc = 0.  n must be <= 2^30.
+ * Scratch is sized before anything is enqueued: STEPS_E_NOMEM (after the
+ * symmetric-to-one-sided fallback) leaves acc untouched. */
 int steps_forces_ctx(steps_ctx *ctx, const double *pos, const double *mass,
                      const double *soft, int64_t n, double *acc);
 /* Same on the default context of the calling thread's current device
@@ -212,7 +216,8 @@ int steps_forces(const double *pos, const double *mass, const double *soft,
  * heuristic's -- one force evaluation each, and keep the fastest for this n:
  * later calls with the same n and precision use it unless a tile is forced.
  * acc [3][n] is scratch output (holds S on return).  Synchronous.  *out
- * receives the chosen shape. */
+ * receives the chosen shape.  Shapes whose scratch does not fit are
+ * skipped; STEPS_E_NOMEM only when none fits. */
 int steps_autotune(steps_ctx *ctx, const double *pos, const double *mass,
                    const double *soft, int64_t n, double *acc,
                    steps_tile *out);
@@ -269,8 +274,9 @@ int steps_kinetic(const double *vel, const double *mass, int64_t n, double a,
  * are always FP64.  da may be negative if a + da > 0.
  * Errors (nothing written): STEPS_E_INVAL for null pointers, n < 0,
  * non-finite a or da, a <= 0 or a + da <= 0 in comoving mode, H0 <= 0,
- * G < 0, reserved != 0, an unknown mode, or H(a)^2 <= 0 anywhere on
- * [a, a + da]. */
+ * G < 0, unknown flag bits, an unknown mode, or H(a)^2 <= 0 anywhere on
+ * [a, a + da]; STEPS_E_NOMEM if the force scratch cannot be allocated
+ * (checked before the first kick is enqueued). */
 int steps_step_ctx(steps_ctx *ctx, double *pos, double *vel,
                    const double *mass, const double *soft, int64_t n,
                    double *acc, double a, double da,

@@ -313,7 +313,7 @@ struct Carve {
 // sorted copy (FP64 [5][n], or the FP32 shadow in mixed mode) -> boxes of
 // tiles of tj particles, all in the context arena, with extra_bytes more
 // carved after them.  Allocation comes first, so an error return has
-// enqueued nothing.
+// enqueued nothing; with enqueue false only the arena is sized.
 struct SortedState {
   const int *perm = nullptr;  // sorted position -> caller index
   double *sorted = nullptr;   // FP64 x, y, z, m, h (kClassF64)
@@ -324,7 +324,7 @@ struct SortedState {
 
 int sort_for_culling(steps_ctx *c, const double *pos, const double *mass,
                      const double *soft, int n, int tj, int cls,
-                     size_t extra_bytes, SortedState *S) {
+                     size_t extra_bytes, SortedState *S, bool enqueue) {
   size_t cub_bytes = 0;
   hipError_t e = steps::sort_pairs(nullptr, &cub_bytes, nullptr, nullptr,
                                    nullptr, nullptr, n, c->stream);
@@ -342,7 +342,7 @@ int sort_for_culling(steps_ctx *c, const double *pos, const double *mass,
                                    : 5 * (size_t)n * sizeof(float));
   const size_t o_extra = cv.take(extra_bytes);
   int rc = ensure(c, c->arena, cv.off, "sort");
-  if (rc) return rc;
+  if (rc || !enqueue) return rc;
   char *base = (char *)c->arena.p;
   double *box = (double *)(base + o_box);
   auto *k0 = (unsigned long long *)(base + o_k0);
@@ -379,11 +379,11 @@ int sort_for_culling(steps_ctx *c, const double *pos, const double *mass,
   return STEPS_OK;
 }
 
-// Enqueue acc <- S(pos) in the context's precision.  Arguments validated.
 // Periodic pair sum: FP64 kernel over Morton-sorted particles, j-split
 // partials reduced in fixed order and scattered to the caller's order.
+// Arguments validated; with enqueue false only the scratch is allocated.
 int run_forces_periodic(steps_ctx *c, const double *pos, const double *mass,
-                        const double *soft, int n, double *acc) {
+                        const double *soft, int n, double *acc, bool enqueue) {
   if (c->precision != STEPS_FP64) {
     return fail(STEPS_E_UNSUPPORTED,
                 "periodic boxes are computed in FP64 only");
@@ -401,7 +401,8 @@ int run_forces_periodic(steps_ctx *c, const double *pos, const double *mass,
   double *out = (double *)c->part.p;
   SortedState S;
   if ((rc = sort_for_culling(c, pos, mass, soft, n, tj, steps::kClassF64, 0,
-                             &S))) {
+                             &S, enqueue)) ||
+      !enqueue) {
     return rc;
   }
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -417,10 +418,11 @@ int run_forces_periodic(steps_ctx *c, const double *pos, const double *mass,
 }
 
 // One force evaluation in launch shape t.  Scratch is allocated before
-// anything is enqueued, so an STEPS_E_NOMEM return has enqueued nothing.
+// anything is enqueued, so an STEPS_E_NOMEM return has enqueued nothing;
+// with enqueue false only the scratch is allocated.
 int run_forces_tile(steps_ctx *c, const double *pos, const double *mass,
                     const double *soft, int n, double *acc,
-                    const steps_tile &t) {
+                    const steps_tile &t, bool enqueue) {
   const int cls = prec_class(c->precision);
   const steps::ForceVariant *v =
       steps::find_force_variant(cls, t.r, t.tj, t.variant);
@@ -455,7 +457,8 @@ int run_forces_tile(steps_ctx *c, const double *pos, const double *mass,
             : 0;
     SortedState S;
     if ((rc = sort_for_culling(c, pos, mass, soft, n, t.tj, cls, jacc_bytes,
-                               &S))) {
+                               &S, enqueue)) ||
+        !enqueue) {
       return rc;
     }
     perm = S.perm;
@@ -470,12 +473,13 @@ int run_forces_tile(steps_ctx *c, const double *pos, const double *mass,
     if (sym && js > 1) L.jacc = (double *)S.extra;
   } else if (cls == steps::kClassMixed) {
     rc = ensure(c, c->shadow, 5 * (size_t)n * sizeof(float), "FP32 shadow");
-    if (rc) return rc;
+    if (rc || !enqueue) return rc;
     e = steps::launch_shadow(pos, mass, soft, n, (float *)c->shadow.p,
                              c->stream);
     if (e != hipSuccess) return hip_fail(e, "shadow kernel launch");
     L.shadow = (const float *)c->shadow.p;
   } else {
+    if (!enqueue) return STEPS_OK;
     L.pos = pos;
     L.mass = mass;
     L.soft = soft;
@@ -499,24 +503,45 @@ int run_forces_tile(steps_ctx *c, const double *pos, const double *mass,
   return STEPS_OK;
 }
 
-int run_forces(steps_ctx *c, const double *pos, const double *mass,
-               const double *soft, int n, double *acc) {
+// Launch shape of the next force evaluation, with all its scratch
+// allocated and nothing enqueued.  An automatically chosen symmetric shape
+// whose partial sums (about 48 Q n bytes) do not fit falls back to the
+// one-sided matrix-core kernel, which needs far less.
+int reserve_forces(steps_ctx *c, int n, steps_tile *t) {
+  *t = steps_tile{0, 0, 0, 0};
   if (n == 0) return STEPS_OK;
   if (c->images != STEPS_IMAGES_NONE) {
-    return run_forces_periodic(c, pos, mass, soft, n, acc);
+    return run_forces_periodic(c, nullptr, nullptr, nullptr, n, nullptr, false);
   }
-  const steps_tile t = choose_tile(c, n);
-  int rc = run_forces_tile(c, pos, mass, soft, n, acc, t);
-  if (rc == STEPS_E_NOMEM && (t.variant & steps::kVarSym) && !c->tile_forced) {
-    // the symmetric kernel's partial sums (about 48 Q n bytes) did not fit:
-    // the one-sided matrix-core kernel needs far less
-    steps_tile u = t;
-    u.variant &= ~steps::kVarSym;
-    u.jsplit = heuristic_jsplit(prec_class(c->precision), n, u.r, u.tj,
-                                u.variant);
-    rc = run_forces_tile(c, pos, mass, soft, n, acc, u);
+  *t = choose_tile(c, n);
+  int rc = run_forces_tile(c, nullptr, nullptr, nullptr, n, nullptr, *t, false);
+  if (rc == STEPS_E_NOMEM && (t->variant & steps::kVarSym) && !c->tile_forced) {
+    t->variant &= ~steps::kVarSym;
+    t->jsplit = heuristic_jsplit(prec_class(c->precision), n, t->r, t->tj,
+                                 t->variant);
+    rc = run_forces_tile(c, nullptr, nullptr, nullptr, n, nullptr, *t, false);
   }
   return rc;
+}
+
+// Enqueue acc <- S(pos) in shape t from reserve_forces.  Arguments validated.
+int enqueue_forces(steps_ctx *c, const double *pos, const double *mass,
+                   const double *soft, int n, double *acc, const steps_tile &t) {
+  if (n == 0) return STEPS_OK;
+  if (c->images != STEPS_IMAGES_NONE) {
+    return run_forces_periodic(c, pos, mass, soft, n, acc, true);
+  }
+  return run_forces_tile(c, pos, mass, soft, n, acc, t, true);
+}
+
+// Enqueue acc <- S(pos) in the context's precision.  Arguments validated;
+// an error return has enqueued nothing.
+int run_forces(steps_ctx *c, const double *pos, const double *mass,
+               const double *soft, int n, double *acc) {
+  steps_tile t;
+  int rc = reserve_forces(c, n, &t);
+  if (rc) return rc;
+  return enqueue_forces(c, pos, mass, soft, n, acc, t);
 }
 
 // Enqueue phi <- G-free softened potential (FP64, unsorted kernel r=2,
@@ -702,6 +727,13 @@ int steps_ctx_destroy(steps_ctx *c) {
 int steps_ctx_set_stream(steps_ctx *c, void *stream) {
   if (!c) return fail(STEPS_E_INVAL, "ctx is NULL");
   std::lock_guard<std::mutex> lk(c->mu);
+  if ((hipStream_t)stream != c->stream) {
+    // scratch may still be in use by work on the old stream; a later resize
+    // frees it after synchronizing the new one only
+    DeviceGuard g(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  }
   c->stream = (hipStream_t)stream;
   return STEPS_OK;
 }
@@ -915,15 +947,23 @@ int steps_autotune(steps_ctx *c, const double *pos, const double *mass,
   if (e == hipSuccess) e = hipEventCreate(&t1);
   steps_tile best = h;
   float best_ms = -1.0f;
-  // the heuristic shape first, also as a warm-up (scratch allocation)
+  // the heuristic shape first, also as a warm-up (scratch allocation); a
+  // shape whose scratch does not fit is skipped
   c->tile = h;
   c->tile_forced = true;
   if (e == hipSuccess) rc = run_forces(c, pos, mass, soft, (int)n, acc);
+  int skipped = rc == STEPS_E_NOMEM ? STEPS_E_NOMEM : STEPS_OK;
+  if (skipped) rc = STEPS_OK;
   for (size_t k = 0; e == hipSuccess && rc == STEPS_OK && k < cands.size(); ++k) {
     c->tile = cands[k];
     e = hipEventRecord(t0, c->stream);
     if (e != hipSuccess) break;
     rc = run_forces(c, pos, mass, soft, (int)n, acc);
+    if (rc == STEPS_E_NOMEM) {
+      skipped = rc;
+      rc = STEPS_OK;
+      continue;
+    }
     if (rc) break;
     e = hipEventRecord(t1, c->stream);
     if (e == hipSuccess) e = hipEventSynchronize(t1);
@@ -940,6 +980,9 @@ int steps_autotune(steps_ctx *c, const double *pos, const double *mass,
   c->tile = was_tile;
   if (e != hipSuccess) return hip_fail(e, "autotune timing");
   if (rc) return rc;
+  if (best_ms < 0.0f && skipped) {
+    return fail(skipped, "no candidate shape fits in device memory");
+  }
   c->tuned.push_back({{cls, n}, best});
   *out = best;
   return STEPS_OK;
@@ -1145,12 +1188,15 @@ static int step_impl(steps_ctx *c, double *pos, double *vel, const double *mass,
                              {acc, 3 * n}}))) {
     return rc;
   }
+  // scratch first: a failing allocation must not leave a half-applied step
+  steps_tile shape;
+  if ((rc = reserve_forces(c, (int)n, &shape))) return rc;
   const double G = bg.g, rad = bg.radial();
   hipError_t e = steps::launch_kick_drift(pos, vel, acc, (int)n, hdt,
                                           G * ai3_0, rad * ai3_0, drag0, dt,
                                           c->stream);
   if (e != hipSuccess) return hip_fail(e, "kick-drift kernel launch");
-  if ((rc = run_forces(c, pos, mass, soft, (int)n, acc))) return rc;
+  if ((rc = enqueue_forces(c, pos, mass, soft, (int)n, acc, shape))) return rc;
   e = steps::launch_kick_end(pos, vel, acc, (int)n, hdt, G * ai3_1,
                              rad * ai3_1, 1.0 / denom, c->stream);
   if (e != hipSuccess) return hip_fail(e, "kick kernel launch");

@@ -202,7 +202,18 @@ def test_impossible_scratch_allocation_is_reported(st):
     assert ei.value.code == st.STEPS_E_NOMEM
     assert "partial-sum" in str(ei.value)
     assert bool((acc == 0).all())
-    del p, m, h, acc
+    # a step in that shape fails the same way before its first kick is
+    # enqueued: positions, velocities and acc stay as they were
+    v = torch.rand((3, n), dtype=torch.float64, device="cuda", generator=g)
+    p0, v0 = p.clone(), v.clone()
+    acc.fill_(1.0)
+    with pytest.raises(st.StepsError) as ei:
+        st.steps_step(p, v, m, h, acc, 0.02, 0.001, st.Cosmology(), ctx=ctx)
+    assert ei.value.code == st.STEPS_E_NOMEM
+    torch.cuda.synchronize()
+    assert torch.equal(p, p0) and torch.equal(v, v0)
+    assert bool((acc == 1.0).all())
+    del p, m, h, acc, v, p0, v0
     torch.cuda.empty_cache()
     ctx.set_tile()                          # back to automatic shapes
     ps = synth.config(1, n=500)
