@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--tile", default=None, metavar="R,TJ,JSPLIT,VARIANT",
+                    help="force the force kernel's launch shape (a compiled "
+                         "variant; JSPLIT 0 = the built-in split), e.g. "
+                         "1,256,0,6 for the one-sided matrix-core kernel")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="finish with one device copy of MIB MiB (a kernel of "
                          "known traffic, to scale HBM byte counters)")
@@ -108,6 +112,8 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = st.Context(0, precision=args.precision, flags=st.STEPS_PROFILE,
                      stream=stream)
+    if args.tile:
+        ctx.set_tile(*(int(x) for x in args.tile.split(",")))
     pos, vel, mass, soft = dev(ps.pos), dev(ps.vel), dev(ps.mass), dev(ps.soft)
     acc = st.steps_forces(pos, mass, soft, ctx=ctx)
 
