@@ -233,6 +233,31 @@ def test_determinism_bitwise(st):
         ctx.close()
 
 
+def test_context_on_user_streams(st):
+    # one context on two user streams in turn, the second call larger so that
+    # its scratch is reallocated after the stream switch: oracle parity on the
+    # first, and the second equal bitwise to the same call on the null stream
+    import torch
+    small, big = synth.config(1, n=3000), synth.config(2, n=40000)
+    ps_, ms_, hs_ = dev(small.pos), dev(small.mass), dev(small.soft)
+    pb, mb, hb = dev(big.pos), dev(big.mass), dev(big.soft)
+    null_ctx = st.Context(0, precision="fp64")
+    want = host(st.steps_forces(pb, mb, hb, ctx=null_ctx))
+    null_ctx.close()
+    torch.cuda.synchronize()
+    ctx = st.Context(0, precision="fp64")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(s1):
+        a = st.steps_forces(ps_, ms_, hs_, ctx=ctx)
+    with torch.cuda.stream(s2):
+        b = st.steps_forces(pb, mb, hb, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.close()
+    err = rel_err(host(a), oracle.forces(small.pos, small.mass, small.soft))
+    assert err.max() <= FP64_TOL
+    assert np.array_equal(host(b), want)
+
+
 def test_default_context_c_entry_point(st):
     # steps_forces (no ctx) through the raw C symbol on the null stream
     import torch
