@@ -238,7 +238,7 @@ def main():
 def force_kernel_name(precision, tile):
     """Name of the force kernel a launch shape runs (as rocprofv3 lists it)."""
     if precision != "fp64":
-        return "k_force_mixed"
+        return "k_force_mixed_sym" if tile["variant"] & 8 else "k_force_mixed"
     if tile["variant"] & 8:
         return "k_force_f64_sym"
     return "k_force_f64_mfma" if tile["variant"] & 4 else "k_force_f64"

@@ -33,6 +33,7 @@ constexpr int64_t kSymMinN = 262144;
 // below this many chunks (the memory cap binds from N ~ 2^22.5) the units
 // no longer fill the device evenly and the one-sided kernel is used
 constexpr int kSymMinChunks = 64;
+constexpr int64_t kMixedSymR4MinN = 524288;
 
 thread_local std::string t_err;
 
@@ -224,6 +225,9 @@ int heuristic_jsplit(int cls, int64_t n, int r, int tj, int variant) {
 //   * FP64 from kSymMinN up: the symmetric matrix-core kernel (variant 14),
 //     15% ahead of the one-sided one at 2^18 and 23-25% at 2^20 and 2^21,
 //     while its memory cap still allows kSymMinChunks chunks;
+//   * mixed with FP64 accumulation from kSymMinN up: the symmetric mixed
+//     kernel (variant 10), 1.31x the one-sided one at 2^18 and 1.45x at
+//     2^21, under the same chunk cap;
 //   * FP64 from kMfmaMinN up: the matrix-core kernel (variant 6, tj 256),
 //     5-7% ahead of the VALU kernel there and 7% behind it at 2^15;
 //   * otherwise FP64 r = 4, mixed r = 2 (fewer registers, more waves to pair
@@ -245,7 +249,15 @@ steps_tile choose_tile(const steps_ctx *c, int64_t n) {
     return t;
   }
   const bool f64 = cls == steps::kClassF64;
-  if (f64 && n >= kMfmaMinN) {
+  if (!f64 && c->precision == STEPS_MIXED_F64ACC && n >= kSymMinN &&
+      sym_chunks(n) >= kSymMinChunks) {
+    // symmetric mixed kernel: r = 2 at 2^18 (14.6 ms against 16.4 for
+    // r = 4), r = 4 from 2^19 on (2^19: 53.5 ms against 56.4; 2^21: 808
+    // against 888)
+    t.r = n >= kMixedSymR4MinN ? 4 : 2;
+    t.tj = 256;
+    t.variant = steps::kVarCull | steps::kVarSym;
+  } else if (f64 && n >= kMfmaMinN) {
     t.r = 1;
     t.tj = 256;
     t.variant = steps::kVarCull | steps::kVarMfma;
@@ -433,6 +445,10 @@ int run_forces_tile(steps_ctx *c, const double *pos, const double *mass,
   }
   const bool cull = (t.variant & steps::kVarCull) != 0;
   const bool sym = (t.variant & steps::kVarSym) != 0;
+  if (sym && c->precision == STEPS_MIXED_KAHAN) {
+    return fail(STEPS_E_UNSUPPORTED,
+                "the symmetric mixed kernel accumulates in FP64 only");
+  }
   int chunk = 0, js = 1;
   split_j(n, t.tj, std::max(1, t.jsplit), &chunk, &js);
   steps::ForceLaunch L;
@@ -779,6 +795,10 @@ int steps_ctx_set_tile(steps_ctx *c, const steps_tile *t) {
   if (t->jsplit < 0 || t->jsplit > 1024) {
     return fail(STEPS_E_INVAL, "jsplit must be in [0, 1024]");
   }
+  if ((t->variant & steps::kVarSym) && c->precision == STEPS_MIXED_KAHAN) {
+    return fail(STEPS_E_INVAL,
+                "the symmetric mixed kernel accumulates in FP64 only");
+  }
   c->tile = *t;
   c->tile_forced = true;
   return STEPS_OK;
@@ -913,7 +933,8 @@ int steps_autotune(steps_ctx *c, const double *pos, const double *mass,
   }
   // candidates: every compiled kernel of the class with r in {1, 2, 4}
   // that the heuristic could choose (FP64 variants 0, 3, 6 and, from
-  // kMfmaMinN, 14; mixed 0 and 2), each at its heuristic j-split times 1/2,
+  // kMfmaMinN, 14; mixed 0, 2 and, from kMfmaMinN with FP64 accumulation,
+  // 10), each at its heuristic j-split times 1/2,
   // 1 and 2 (the symmetric kernel's chunk count only times 1/2 and 1: its
   // heuristic count is already the largest within the memory cap)
   std::vector<steps_tile> cands;
@@ -926,7 +947,8 @@ int steps_autotune(steps_ctx *c, const double *pos, const double *mass,
         cls == steps::kClassF64
             ? (v.variant == 0 || v.variant == 3 || v.variant == 6 ||
                (sym && n >= kMfmaMinN))
-            : (v.variant == 0 || v.variant == 2);
+            : (v.variant == 0 || v.variant == 2 ||
+               (sym && n >= kMfmaMinN && c->precision == STEPS_MIXED_F64ACC));
     if (v.cls != cls || !usable || (v.r != 1 && v.r != 2 && v.r != 4)) continue;
     const int hj = heuristic_jsplit(cls, n, v.r, v.tj, v.variant);
     {

@@ -1011,6 +1011,225 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric mixed-precision evaluation (Newton's third law, Sec. 2.2 Eq. 8:
+// the pair term is antisymmetric), on the units and output layout of the
+// FP64 symmetric kernel.  In an off-diagonal unit (R, s) each wave takes
+// 64 R particles of chunk R (R per lane) against every 256-particle tile of
+// chunk s, the tile in four parts of 64.  In step t of a part, lane l pairs
+// its particles with particle (l + t) mod 64 of the part, read from LDS: over
+// 64 steps every lane meets every j of the part once, and within a step no
+// two lanes share a j.  One FP32 weight w' = F(r, h)/r per pair serves both
+// sides: the i-side sums m_j w' d in registers, and the lane's R terms
+// m_i w' d of the step are added into the wave's own FP32 j-sums in LDS by
+// plain read-modify-write (one lane per address and step, so the order of
+// additions is fixed; LDS float atomics measured 7x slower overall).  Per tile,
+// the i-side partial is added into FP64, and the four waves' j-sums are
+// added in wave order into the unit's FP64 (value, error) accumulator.  The
+// cross-lane traffic goes through the LDS pipe, so the vector ALU issues only
+// the pair arithmetic: one v_rsq_f32 per unordered pair instead of two.
+// ---------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ void sym_block_mixed(
+    const float *__restrict__ shadow, int stride, int i0, int iend, int jbeg,
+    int jend, const double *__restrict__ tinfo, double *__restrict__ out,
+    double *__restrict__ jacc, int chunk, bool first, float4 *tpos,
+    float *tsoft, float *jl) {
+  constexpr int TJ = 256;
+  static_assert(TJ == kBlock, "one thread per tile particle");
+  const int tid = threadIdx.x;
+  const int l = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wbase = i0 + wv * 64 * R;
+  const int last = iend - 1;
+  const float *X = shadow, *Y = shadow + stride, *Z = shadow + 2 * (size_t)stride;
+  const float *M = shadow + 3 * (size_t)stride, *H = shadow + 4 * (size_t)stride;
+  float *jw = jl + (size_t)wv * 3 * TJ;  // this wave's j-sums [3][TJ]
+
+  // lanes past iend take the position of the last particle (inside the wave
+  // box, so far tiles keep r > 0) and zero mass
+  float xi[R], yi[R], zi[R], mi[R], hi[R];
+  bool valid[R];
+  double ax[R], ay[R], az[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = wbase + 64 * r + l;
+    valid[r] = i < iend;
+    const int ic = min(i, last);
+    xi[r] = X[ic];
+    yi[r] = Y[ic];
+    zi[r] = Z[ic];
+    hi[r] = H[ic];
+    mi[r] = valid[r] ? M[ic] : 0.0f;
+    ax[r] = ay[r] = az[r] = 0.0;
+  }
+  const bool live = wbase < iend;  // wave-uniform: any valid i
+  double wb[7];
+  wave_box<R, float>(xi, yi, zi, hi, valid, wb);
+
+  for (int jt = jbeg; jt < jend; jt += TJ) {
+    __syncthreads();
+    {
+      const int j = min(jt + tid, jend - 1);
+      tpos[tid] = float4{X[j], Y[j], Z[j], (jt + tid < jend) ? M[j] : 0.0f};
+      tsoft[tid] = H[j];
+    }
+    for (int k = l; k < 3 * TJ; k += 64) jw[k] = 0.0f;
+    __syncthreads();
+
+    const bool far = tile_is_far(tinfo + (size_t)((jt - jbeg) / TJ) * 8, wb);
+    float tx[R], ty[R], tz[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) tx[r] = ty[r] = tz[r] = 0.0f;
+    if (live) {
+      for (int q = 0; q < TJ; q += 64) {
+        if (far) {
+#pragma unroll 2
+          for (int t = 0; t < 64; ++t) {
+            const int jj = q + ((l + t) & 63);
+            const float4 p = tpos[jj];
+            // this j's running sums, read before the pair arithmetic that
+            // hides their latency (plain read-modify-write: one lane per
+            // address within a step, and a wave's LDS accesses complete in
+            // order)
+            float jx = jw[jj], jy = jw[TJ + jj], jz = jw[2 * TJ + jj];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const float dx = p.x - xi[r], dy = p.y - yi[r], dz = p.z - zi[r];
+              const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+              const float y = __builtin_amdgcn_rsqf(r2);
+              const float y3 = (y * y) * y;
+              const float wi = p.w * y3, wj = mi[r] * y3;
+              tx[r] = fmaf(wi, dx, tx[r]);
+              ty[r] = fmaf(wi, dy, ty[r]);
+              tz[r] = fmaf(wi, dz, tz[r]);
+              jx = fmaf(wj, dx, jx);
+              jy = fmaf(wj, dy, jy);
+              jz = fmaf(wj, dz, jz);
+            }
+            jw[jj] = jx;
+            jw[TJ + jj] = jy;
+            jw[2 * TJ + jj] = jz;
+          }
+        } else {
+          // softening tested per pair (coincident pairs take the softened
+          // branch, which gives 0)
+#pragma unroll 2
+          for (int t = 0; t < 64; ++t) {
+            const int jj = q + ((l + t) & 63);
+            const float4 p = tpos[jj];
+            const float hj = tsoft[jj];
+            float jx = jw[jj], jy = jw[TJ + jj], jz = jw[2 * TJ + jj];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const float dx = p.x - xi[r], dy = p.y - yi[r], dz = p.z - zi[r];
+              const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+              const float h = hj + hi[r];
+              const float y = __builtin_amdgcn_rsqf(r2);
+              float w = (y * y) * y;
+              if (r2 <= h * h) w = soft_w32(r2, h, 1.0f);
+              const float wi = p.w * w, wj = mi[r] * w;
+              tx[r] = fmaf(wi, dx, tx[r]);
+              ty[r] = fmaf(wi, dy, ty[r]);
+              tz[r] = fmaf(wi, dz, tz[r]);
+              jx = fmaf(wj, dx, jx);
+              jy = fmaf(wj, dy, jy);
+              jz = fmaf(wj, dz, jz);
+            }
+            jw[jj] = jx;
+            jw[TJ + jj] = jy;
+            jw[2 * TJ + jj] = jz;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      ax[r] += (double)tx[r];
+      ay[r] += (double)ty[r];
+      az[r] += (double)tz[r];
+    }
+    // this thread's accumulator entry (j = jt + tid), read while the other
+    // waves finish
+    const bool jown = jt + tid < jend;
+    const size_t jo = (size_t)(jt + tid - jbeg);
+    double acc6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (!first && jown) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc6[c] = jacc[(size_t)c * chunk + jo];
+    }
+    __syncthreads();
+    if (jown) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        // the pull of i on j is m_i w' (x_i - x_j) = -(m_i w' d); the
+        // waves' FP32 sums (64 R terms each) are added in FP64
+        const double f = -((((double)jl[c * TJ + tid] +
+                             (double)jl[(3 + c) * TJ + tid]) +
+                            (double)jl[(6 + c) * TJ + tid]) +
+                           (double)jl[(9 + c) * TJ + tid]);
+        if (first) {
+          acc6[c] = f;
+          acc6[3 + c] = 0.0;
+        } else {
+          two_sum_add(acc6[c], acc6[3 + c], f);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) jacc[(size_t)c * chunk + jo] = acc6[c];
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = wbase + 64 * r + l;
+    if (valid[r]) {
+      out[i] = ax[r];
+      out[(size_t)stride + i] = ay[r];
+      out[2 * (size_t)stride + i] = az[r];
+    }
+  }
+}
+
+// Symmetric mixed kernel: the unit grid of k_force_f64_sym; diagonal units
+// run the one-sided mixed block (FP64 accumulation) into plane s.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_force_mixed_sym(
+    const float *__restrict__ shadow, int n, int chunk, int nchunks,
+    const double *__restrict__ tinfo, double *__restrict__ iplane,
+    double *__restrict__ jacc) {
+  __shared__ float4 tpos[256];
+  __shared__ float tsoft[256];
+  __shared__ float jl[4 * 3 * 256];
+  const int nsym = nchunks * (nchunks - 1) / 2;
+  const int u = blockIdx.x;
+  int cr, cs;
+  if (u < nsym) {
+    cs = (int)((1.0 + sqrt(1.0 + 8.0 * (double)u)) * 0.5);
+    while (cs * (cs - 1) / 2 > u) --cs;
+    while ((cs + 1) * cs / 2 <= u) ++cs;
+    cr = u - cs * (cs - 1) / 2;
+  } else {
+    cr = cs = u - nsym;
+  }
+  const int ibeg = cr * chunk, iend = min(n, ibeg + chunk);
+  const int jbeg = cs * chunk, jend = min(n, jbeg + chunk);
+  double *out = iplane + (size_t)cs * 3 * (size_t)n;
+  const double *ti = tinfo + (size_t)(jbeg / 256) * 8;
+  if (cr == cs) {
+    for (int i0 = ibeg; i0 < iend; i0 += kBlock * R) {
+      force_block_mixed<R, 256, false, true>(shadow, n, i0, iend, jbeg, jend,
+                                             ti, out, tpos, tsoft);
+    }
+    return;
+  }
+  double *ja = jacc + (size_t)u * 6 * (size_t)chunk;
+  for (int i0 = ibeg; i0 < iend; i0 += kBlock * R) {
+    sym_block_mixed<R>(shadow, n, i0, iend, jbeg, jend, ti, out, ja, chunk,
+                       i0 == ibeg, tpos, tsoft, jl);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Ensemble kernels: a persistent grid pulls work items from an atomic
 // counter until none are left (every block then returns, so the grid always
 // drains).  Item k is the block of particles [it.x, it.y) of one member
@@ -1121,6 +1340,22 @@ hipError_t launch_f64_sym(const ForceLaunch &L, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Symmetric mixed kernel (FP64 accumulation only): the chunk layout is
+// checked as for the FP64 symmetric kernel.
+template <int R>
+hipError_t launch_mixed_sym(const ForceLaunch &L, hipStream_t s) {
+  const int q = L.jsplit;
+  if (L.kahan || !L.shadow || L.jchunk <= 0 || L.jchunk % 256 != 0 || q < 1 ||
+      q > 4096 || (long long)(q - 1) * L.jchunk >= L.n ||
+      (long long)q * L.jchunk < L.n || (q > 1 && !L.jacc) || !L.tinfo) {
+    return hipErrorInvalidValue;
+  }
+  const int units = q * (q + 1) / 2;
+  hipLaunchKernelGGL((k_force_mixed_sym<R>), dim3(units), dim3(kBlock), 0, s,
+                     L.shadow, L.n, L.jchunk, q, L.tinfo, L.out, L.jacc);
+  return hipGetLastError();
+}
+
 template <int R, int TJ, bool CULL>
 hipError_t launch_mixed(const ForceLaunch &L, hipStream_t s) {
   dim3 grid(ceil_div(L.n, (long long)kBlock * R), L.jsplit);
@@ -1187,7 +1422,8 @@ hipError_t launch_batch_mixed(const BatchLaunch &L, hipStream_t s) {
 // variant bits: 1 = FP64 weight without the e^2 term; 2 = sorted input with
 // (wave, tile) culling of the softening test; 4 = matrix-core far field
 // (with 2: sorted input; a wave owns 64 particles, so it is listed as r = 1);
-// 8 = symmetric units (with 2 and 4; jsplit is the chunk count).
+// 8 = symmetric units (FP64: with 2 and 4; mixed: with 2, FP64
+// accumulation only; jsplit is the chunk count).
 #define F64_SET(R)                                                  \
   {kClassF64, R, 128, 0, launch_f64<R, 128, true, false>},          \
       {kClassF64, R, 128, 1, launch_f64<R, 128, false, false>},     \
@@ -1203,6 +1439,8 @@ const ForceVariant kVariants[] = {
     {kClassF64, 1, 256, 6, launch_f64_mfma<256>},
     {kClassF64, 1, 256, 14, launch_f64_sym<256>},
     MIXED_SET(1, 128),  MIXED_SET(2, 256),  MIXED_SET(4, 256),  MIXED_SET(8, 256),
+    {kClassMixed, 2, 256, 10, launch_mixed_sym<2>},
+    {kClassMixed, 4, 256, 10, launch_mixed_sym<4>},
 };
 
 // ensemble variants: always culled (the ensemble keeps its state sorted)

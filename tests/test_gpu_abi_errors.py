@@ -130,6 +130,11 @@ def test_bad_tile_rejected(st):
     ctx.set_precision("mixed")
     with pytest.raises(st.StepsError):
         ctx.set_tile(4, 128, 1, 1)   # FP64-only variant
+    ctx.set_tile(4, 256, 0, 10)      # the symmetric mixed kernel
+    ctx.set_tile()
+    ctx.set_precision("kahan")
+    with pytest.raises(st.StepsError):
+        ctx.set_tile(4, 256, 0, 10)  # FP64 accumulation only
     ctx.close()
 
 
