@@ -125,13 +125,12 @@ typedef struct steps_cosmology {
  *   8  each pair between two different chunks of the sorted set evaluated
  *      once and applied to both particles (Newton's third law); jsplit is
  *      then the number of chunks.  STEPS_FP64: with 2 and 4 (r = 1,
- *      tj = 256).  STEPS_MIXED_F64ACC: with 2 (r 2 or 4, tj = 256); not
- *      with STEPS_MIXED_KAHAN.
+ *      tj = 256).  Mixed modes: with 2 (r 2 or 4, tj = 256).
  * Compiled combinations: FP64 0, 1, 2, 3 (r 1, 2, 4, 8; tj 128), 6 (tj 128
- * and 256), 14 (tj 256); mixed modes 0 and 2, and 10 (r 2 and 4, tj 256)
- * with FP64 accumulation.  Defaults from N = 2^18 (while the chunk cap
- * allows 64 chunks): FP64 variant 14; mixed with FP64 accumulation
- * variant 10, r = 2 below 2^19 and r = 4 from there. */
+ * and 256), 14 (tj 256); mixed modes 0 and 2, and 10 (r 2 and 4,
+ * tj 256).  Defaults from N = 2^18 (while the chunk cap allows 64 chunks):
+ * FP64 variant 14; mixed modes variant 10, r = 2 below 2^19 and r = 4
+ * from there. */
 typedef struct steps_tile {
   int32_t r;
   int32_t tj;

@@ -225,9 +225,9 @@ int heuristic_jsplit(int cls, int64_t n, int r, int tj, int variant) {
 //   * FP64 from kSymMinN up: the symmetric matrix-core kernel (variant 14),
 //     15% ahead of the one-sided one at 2^18 and 23-25% at 2^20 and 2^21,
 //     while its memory cap still allows kSymMinChunks chunks;
-//   * mixed with FP64 accumulation from kSymMinN up: the symmetric mixed
-//     kernel (variant 10), 1.31x the one-sided one at 2^18 and 1.45x at
-//     2^21, under the same chunk cap;
+//   * mixed from kSymMinN up: the symmetric mixed kernel (variant 10),
+//     1.31x the one-sided one at 2^18 and 1.45x at 2^21 (FP64
+//     accumulation), under the same chunk cap;
 //   * FP64 from kMfmaMinN up: the matrix-core kernel (variant 6, tj 256),
 //     5-7% ahead of the VALU kernel there and 7% behind it at 2^15;
 //   * otherwise FP64 r = 4, mixed r = 2 (fewer registers, more waves to pair
@@ -249,8 +249,7 @@ steps_tile choose_tile(const steps_ctx *c, int64_t n) {
     return t;
   }
   const bool f64 = cls == steps::kClassF64;
-  if (!f64 && c->precision == STEPS_MIXED_F64ACC && n >= kSymMinN &&
-      sym_chunks(n) >= kSymMinChunks) {
+  if (!f64 && n >= kSymMinN && sym_chunks(n) >= kSymMinChunks) {
     // symmetric mixed kernel: r = 2 at 2^18 (14.6 ms against 16.4 for
     // r = 4), r = 4 from 2^19 on (2^19: 53.5 ms against 56.4; 2^21: 808
     // against 888)
@@ -445,10 +444,6 @@ int run_forces_tile(steps_ctx *c, const double *pos, const double *mass,
   }
   const bool cull = (t.variant & steps::kVarCull) != 0;
   const bool sym = (t.variant & steps::kVarSym) != 0;
-  if (sym && c->precision == STEPS_MIXED_KAHAN) {
-    return fail(STEPS_E_UNSUPPORTED,
-                "the symmetric mixed kernel accumulates in FP64 only");
-  }
   int chunk = 0, js = 1;
   split_j(n, t.tj, std::max(1, t.jsplit), &chunk, &js);
   steps::ForceLaunch L;
@@ -795,10 +790,6 @@ int steps_ctx_set_tile(steps_ctx *c, const steps_tile *t) {
   if (t->jsplit < 0 || t->jsplit > 1024) {
     return fail(STEPS_E_INVAL, "jsplit must be in [0, 1024]");
   }
-  if ((t->variant & steps::kVarSym) && c->precision == STEPS_MIXED_KAHAN) {
-    return fail(STEPS_E_INVAL,
-                "the symmetric mixed kernel accumulates in FP64 only");
-  }
   c->tile = *t;
   c->tile_forced = true;
   return STEPS_OK;
@@ -933,8 +924,8 @@ int steps_autotune(steps_ctx *c, const double *pos, const double *mass,
   }
   // candidates: every compiled kernel of the class with r in {1, 2, 4}
   // that the heuristic could choose (FP64 variants 0, 3, 6 and, from
-  // kMfmaMinN, 14; mixed 0, 2 and, from kMfmaMinN with FP64 accumulation,
-  // 10), each at its heuristic j-split times 1/2,
+  // kMfmaMinN, 14; mixed 0, 2 and, from kMfmaMinN, 10), each at its
+  // heuristic j-split times 1/2,
   // 1 and 2 (the symmetric kernel's chunk count only times 1/2 and 1: its
   // heuristic count is already the largest within the memory cap)
   std::vector<steps_tile> cands;
@@ -947,8 +938,7 @@ int steps_autotune(steps_ctx *c, const double *pos, const double *mass,
         cls == steps::kClassF64
             ? (v.variant == 0 || v.variant == 3 || v.variant == 6 ||
                (sym && n >= kMfmaMinN))
-            : (v.variant == 0 || v.variant == 2 ||
-               (sym && n >= kMfmaMinN && c->precision == STEPS_MIXED_F64ACC));
+            : (v.variant == 0 || v.variant == 2 || (sym && n >= kMfmaMinN));
     if (v.cls != cls || !usable || (v.r != 1 && v.r != 2 && v.r != 4)) continue;
     const int hj = heuristic_jsplit(cls, n, v.r, v.tj, v.variant);
     {

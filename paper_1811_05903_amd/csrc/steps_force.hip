@@ -1023,12 +1023,13 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(
 // m_i w' d of the step are added into the wave's own FP32 j-sums in LDS by
 // plain read-modify-write (one lane per address and step, so the order of
 // additions is fixed; LDS float atomics measured 7x slower overall).  Per tile,
-// the i-side partial is added into FP64, and the four waves' j-sums are
-// added in wave order into the unit's FP64 (value, error) accumulator.  The
+// the i-side partial is added into FP64 (or a Kahan FP32 pair), and the four
+// waves' j-sums are added in wave order into the unit's (value, error)
+// accumulator: FP64 TwoSum, or a Kahan FP32 step kept as (sum, -comp).  The
 // cross-lane traffic goes through the LDS pipe, so the vector ALU issues only
 // the pair arithmetic: one v_rsq_f32 per unordered pair instead of two.
 // ---------------------------------------------------------------------------
-template <int R>
+template <int R, bool KAHAN>
 __device__ __forceinline__ void sym_block_mixed(
     const float *__restrict__ shadow, int stride, int i0, int iend, int jbeg,
     int jend, const double *__restrict__ tinfo, double *__restrict__ out,
@@ -1049,7 +1050,8 @@ __device__ __forceinline__ void sym_block_mixed(
   // box, so far tiles keep r > 0) and zero mass
   float xi[R], yi[R], zi[R], mi[R], hi[R];
   bool valid[R];
-  double ax[R], ay[R], az[R];
+  double ax[R], ay[R], az[R];                      // FP64 accumulation
+  float sx[R], sy[R], sz[R], cx[R], cy[R], cz[R];  // Kahan accumulation
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int i = wbase + 64 * r + l;
@@ -1061,6 +1063,7 @@ __device__ __forceinline__ void sym_block_mixed(
     hi[r] = H[ic];
     mi[r] = valid[r] ? M[ic] : 0.0f;
     ax[r] = ay[r] = az[r] = 0.0;
+    sx[r] = sy[r] = sz[r] = cx[r] = cy[r] = cz[r] = 0.0f;
   }
   const bool live = wbase < iend;  // wave-uniform: any valid i
   double wb[7];
@@ -1144,9 +1147,16 @@ __device__ __forceinline__ void sym_block_mixed(
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      ax[r] += (double)tx[r];
-      ay[r] += (double)ty[r];
-      az[r] += (double)tz[r];
+      if (KAHAN) {
+        float yv, t;
+        yv = tx[r] - cx[r]; t = sx[r] + yv; cx[r] = (t - sx[r]) - yv; sx[r] = t;
+        yv = ty[r] - cy[r]; t = sy[r] + yv; cy[r] = (t - sy[r]) - yv; sy[r] = t;
+        yv = tz[r] - cz[r]; t = sz[r] + yv; cz[r] = (t - sz[r]) - yv; sz[r] = t;
+      } else {
+        ax[r] += (double)tx[r];
+        ay[r] += (double)ty[r];
+        az[r] += (double)tz[r];
+      }
     }
     // this thread's accumulator entry (j = jt + tid), read while the other
     // waves finish
@@ -1161,17 +1171,35 @@ __device__ __forceinline__ void sym_block_mixed(
     if (jown) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        // the pull of i on j is m_i w' (x_i - x_j) = -(m_i w' d); the
-        // waves' FP32 sums (64 R terms each) are added in FP64
-        const double f = -((((double)jl[c * TJ + tid] +
-                             (double)jl[(3 + c) * TJ + tid]) +
-                            (double)jl[(6 + c) * TJ + tid]) +
-                           (double)jl[(9 + c) * TJ + tid]);
-        if (first) {
-          acc6[c] = f;
-          acc6[3 + c] = 0.0;
+        // the pull of i on j is m_i w' (x_i - x_j) = -(m_i w' d)
+        if (KAHAN) {
+          // the waves' sums added in FP32, then a Kahan FP32 step; the
+          // accumulator keeps (sum, -compensation), so that value + error
+          // is the compensated total
+          const float f = -(((jl[c * TJ + tid] + jl[(3 + c) * TJ + tid]) +
+                             jl[(6 + c) * TJ + tid]) +
+                            jl[(9 + c) * TJ + tid]);
+          if (first) {
+            acc6[c] = (double)f;
+            acc6[3 + c] = 0.0;
+          } else {
+            const float s0 = (float)acc6[c], c0 = -(float)acc6[3 + c];
+            const float yv = f - c0, t = s0 + yv;
+            acc6[3 + c] = -(double)((t - s0) - yv);
+            acc6[c] = (double)t;
+          }
         } else {
-          two_sum_add(acc6[c], acc6[3 + c], f);
+          // the waves' FP32 sums (64 R terms each) are added in FP64
+          const double f = -((((double)jl[c * TJ + tid] +
+                               (double)jl[(3 + c) * TJ + tid]) +
+                              (double)jl[(6 + c) * TJ + tid]) +
+                             (double)jl[(9 + c) * TJ + tid]);
+          if (first) {
+            acc6[c] = f;
+            acc6[3 + c] = 0.0;
+          } else {
+            two_sum_add(acc6[c], acc6[3 + c], f);
+          }
         }
       }
 #pragma unroll
@@ -1183,16 +1211,22 @@ __device__ __forceinline__ void sym_block_mixed(
   for (int r = 0; r < R; ++r) {
     const int i = wbase + 64 * r + l;
     if (valid[r]) {
-      out[i] = ax[r];
-      out[(size_t)stride + i] = ay[r];
-      out[2 * (size_t)stride + i] = az[r];
+      if (KAHAN) {
+        out[i] = (double)sx[r] - (double)cx[r];
+        out[(size_t)stride + i] = (double)sy[r] - (double)cy[r];
+        out[2 * (size_t)stride + i] = (double)sz[r] - (double)cz[r];
+      } else {
+        out[i] = ax[r];
+        out[(size_t)stride + i] = ay[r];
+        out[2 * (size_t)stride + i] = az[r];
+      }
     }
   }
 }
 
 // Symmetric mixed kernel: the unit grid of k_force_f64_sym; diagonal units
-// run the one-sided mixed block (FP64 accumulation) into plane s.
-template <int R>
+// run the one-sided mixed block (same accumulation) into plane s.
+template <int R, bool KAHAN>
 __global__ __launch_bounds__(kBlock) void k_force_mixed_sym(
     const float *__restrict__ shadow, int n, int chunk, int nchunks,
     const double *__restrict__ tinfo, double *__restrict__ iplane,
@@ -1217,15 +1251,15 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed_sym(
   const double *ti = tinfo + (size_t)(jbeg / 256) * 8;
   if (cr == cs) {
     for (int i0 = ibeg; i0 < iend; i0 += kBlock * R) {
-      force_block_mixed<R, 256, false, true>(shadow, n, i0, iend, jbeg, jend,
+      force_block_mixed<R, 256, KAHAN, true>(shadow, n, i0, iend, jbeg, jend,
                                              ti, out, tpos, tsoft);
     }
     return;
   }
   double *ja = jacc + (size_t)u * 6 * (size_t)chunk;
   for (int i0 = ibeg; i0 < iend; i0 += kBlock * R) {
-    sym_block_mixed<R>(shadow, n, i0, iend, jbeg, jend, ti, out, ja, chunk,
-                       i0 == ibeg, tpos, tsoft, jl);
+    sym_block_mixed<R, KAHAN>(shadow, n, i0, iend, jbeg, jend, ti, out, ja,
+                              chunk, i0 == ibeg, tpos, tsoft, jl);
   }
 }
 
@@ -1340,19 +1374,25 @@ hipError_t launch_f64_sym(const ForceLaunch &L, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Symmetric mixed kernel (FP64 accumulation only): the chunk layout is
-// checked as for the FP64 symmetric kernel.
+// Symmetric mixed kernel: the chunk layout is checked as for the FP64
+// symmetric kernel.
 template <int R>
 hipError_t launch_mixed_sym(const ForceLaunch &L, hipStream_t s) {
   const int q = L.jsplit;
-  if (L.kahan || !L.shadow || L.jchunk <= 0 || L.jchunk % 256 != 0 || q < 1 ||
+  if (!L.shadow || L.jchunk <= 0 || L.jchunk % 256 != 0 || q < 1 ||
       q > 4096 || (long long)(q - 1) * L.jchunk >= L.n ||
       (long long)q * L.jchunk < L.n || (q > 1 && !L.jacc) || !L.tinfo) {
     return hipErrorInvalidValue;
   }
   const int units = q * (q + 1) / 2;
-  hipLaunchKernelGGL((k_force_mixed_sym<R>), dim3(units), dim3(kBlock), 0, s,
-                     L.shadow, L.n, L.jchunk, q, L.tinfo, L.out, L.jacc);
+  if (L.kahan) {
+    hipLaunchKernelGGL((k_force_mixed_sym<R, true>), dim3(units), dim3(kBlock),
+                       0, s, L.shadow, L.n, L.jchunk, q, L.tinfo, L.out, L.jacc);
+  } else {
+    hipLaunchKernelGGL((k_force_mixed_sym<R, false>), dim3(units),
+                       dim3(kBlock), 0, s, L.shadow, L.n, L.jchunk, q, L.tinfo,
+                       L.out, L.jacc);
+  }
   return hipGetLastError();
 }
 
@@ -1422,8 +1462,8 @@ hipError_t launch_batch_mixed(const BatchLaunch &L, hipStream_t s) {
 // variant bits: 1 = FP64 weight without the e^2 term; 2 = sorted input with
 // (wave, tile) culling of the softening test; 4 = matrix-core far field
 // (with 2: sorted input; a wave owns 64 particles, so it is listed as r = 1);
-// 8 = symmetric units (FP64: with 2 and 4; mixed: with 2, FP64
-// accumulation only; jsplit is the chunk count).
+// 8 = symmetric units (FP64: with 2 and 4; mixed: with 2; jsplit is the
+// chunk count).
 #define F64_SET(R)                                                  \
   {kClassF64, R, 128, 0, launch_f64<R, 128, true, false>},          \
       {kClassF64, R, 128, 1, launch_f64<R, 128, false, false>},     \

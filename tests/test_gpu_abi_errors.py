@@ -131,10 +131,10 @@ def test_bad_tile_rejected(st):
     with pytest.raises(st.StepsError):
         ctx.set_tile(4, 128, 1, 1)   # FP64-only variant
     ctx.set_tile(4, 256, 0, 10)      # the symmetric mixed kernel
-    ctx.set_tile()
-    ctx.set_precision("kahan")
+    ctx.set_precision("kahan")       # same class: the shape stays valid
+    assert ctx.get_tile(262144)["variant"] == 10
     with pytest.raises(st.StepsError):
-        ctx.set_tile(4, 256, 0, 10)  # FP64 accumulation only
+        ctx.set_tile(1, 256, 0, 14)  # FP64-only variant
     ctx.close()
 
 

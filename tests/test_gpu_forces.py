@@ -89,10 +89,10 @@ def test_every_launch_shape(st):
     ref = oracle.forces(pos, mass, soft)
     shapes = _variants(st)
     # FP64: 4 r x 4 variants + two matrix-core tiles + the symmetric one;
-    # mixed: 4 r x 2 variants + the symmetric one at r = 2 and 4; Kahan:
-    # 4 r x 2 variants; 3 splits each (for the symmetric kernels 1, 3 and 7
-    # chunks, the last one a single particle)
-    assert len(shapes) == (19 + 10 + 8) * 3
+    # mixed and Kahan: 4 r x 2 variants + the symmetric one at r = 2 and 4;
+    # 3 splits each (for the symmetric kernels 1, 3 and 7 chunks, the last
+    # one a single particle)
+    assert len(shapes) == (19 + 10 + 10) * 3
     ctxs = {p: st.Context(0, precision=p) for p in ("fp64", "mixed", "kahan")}
     for prec, r, tj, var, js in shapes:
         ctx = ctxs[prec]
@@ -202,17 +202,18 @@ def test_symmetric_kernel_parity(st, kind, q):
 
 @pytest.mark.parametrize("r,q", [(2, 2), (4, 3), (2, 8), (4, 0)])
 @pytest.mark.parametrize("kind", ["stereo", "clustered"])
-def test_symmetric_mixed_kernel_parity(st, kind, r, q):
-    # variant 10: FP32 pairs, one weight per pair for both particles, FP64
-    # accumulation; ragged n, q chunks (0: the built-in count), r particles
-    # per lane; the clustered set has softened and coincident pairs between
-    # chunks.  Mixed bar, and bitwise repeats
+@pytest.mark.parametrize("prec", ["mixed", "kahan"])
+def test_symmetric_mixed_kernel_parity(st, prec, kind, r, q):
+    # variant 10: FP32 pairs, one weight per pair for both particles, FP64 or
+    # Kahan FP32 accumulation; ragged n, q chunks (0: the built-in count), r
+    # particles per lane; the clustered set has softened and coincident pairs
+    # between chunks.  Mixed bar, and bitwise repeats
     if kind == "stereo":
         ps = synth.config(2, n=20001)
         pos, mass, soft = ps.pos, ps.mass, ps.soft
     else:
         pos, mass, soft = clustered(9000, 37, 0.1)
-    ctx = st.Context(0, precision="mixed")
+    ctx = st.Context(0, precision=prec)
     ctx.set_tile(r, 256, q, 10)
     got = _gpu_forces(st, pos, mass, soft, ctx)
     again = _gpu_forces(st, pos, mass, soft, ctx)
@@ -221,25 +222,26 @@ def test_symmetric_mixed_kernel_parity(st, kind, r, q):
     assert np.array_equal(got, again)
     assert tile["variant"] == 10
     err = rel_err(got, oracle.forces(pos, mass, soft))
-    _report("mixed symmetric %s r=%d q=%d (jsplit %d)" % (kind, r, q, tile["jsplit"]), err)
+    _report("%s symmetric %s r=%d q=%d (jsplit %d)" % (prec, kind, r, q, tile["jsplit"]), err)
     assert np.all(np.isfinite(got))
     assert np.median(err) <= 1e-5
     assert err.max() <= 1e-3
 
 
-def test_symmetric_mixed_default_full_size_sampled(st):
+@pytest.mark.parametrize("prec", ["mixed", "kahan"])
+def test_symmetric_mixed_default_full_size_sampled(st, prec):
     # N = 2^18 + 37 in the default mixed shape (the symmetric kernel, ragged
     # last chunk); the last 40 rows and 216 others
     n = 262144 + 37
     ps = synth.config(2, n=n)
-    ctx = st.Context(0, precision="mixed")
+    ctx = st.Context(0, precision=prec)
     assert ctx.get_tile(n)["variant"] == 10
     got = _gpu_forces(st, ps.pos, ps.mass, ps.soft, ctx)
     ctx.close()
     rng = np.random.default_rng(7)
     idx = np.concatenate([np.arange(n - 40, n), rng.choice(n - 40, 216, replace=False)])
     err = rel_err(got[:, idx], oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx))
-    _report("mixed symmetric ragged n=%d" % n, err)
+    _report("%s symmetric ragged n=%d" % (prec, n), err)
     assert np.median(err) <= 1e-5
     assert err.max() <= 1e-3
 
