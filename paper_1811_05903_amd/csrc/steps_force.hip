@@ -1029,6 +1029,14 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(
 // cross-lane traffic goes through the LDS pipe, so the vector ALU issues only
 // the pair arithmetic: one v_rsq_f32 per unordered pair instead of two.
 // ---------------------------------------------------------------------------
+// Orders one rotation step's LDS j-sum stores before the next step's loads.
+// Step t + 1 of lane l - 1 reads the word that lane l wrote in step t; from
+// one thread's view the two addresses differ, so without a fence the
+// compiler could move the load above the store.  The hardware needs no wait:
+// a wave's LDS instructions execute in issue order.  The empty asm with a
+// memory clobber is a compiler-only barrier (it emits no instruction).
+__device__ __forceinline__ void lds_step_fence() { asm volatile("" ::: "memory"); }
+
 template <int R, bool KAHAN>
 __device__ __forceinline__ void sym_block_mixed(
     const float *__restrict__ shadow, int stride, int i0, int iend, int jbeg,
@@ -1092,8 +1100,8 @@ __device__ __forceinline__ void sym_block_mixed(
             const float4 p = tpos[jj];
             // this j's running sums, read before the pair arithmetic that
             // hides their latency (plain read-modify-write: one lane per
-            // address within a step, and a wave's LDS accesses complete in
-            // order)
+            // address within a step; the word lane l writes here is read by
+            // lane l - 1 in the next step, ordered by lds_step_fence below)
             float jx = jw[jj], jy = jw[TJ + jj], jz = jw[2 * TJ + jj];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -1112,6 +1120,7 @@ __device__ __forceinline__ void sym_block_mixed(
             jw[jj] = jx;
             jw[TJ + jj] = jy;
             jw[2 * TJ + jj] = jz;
+            lds_step_fence();
           }
         } else {
           // softening tested per pair (coincident pairs take the softened
@@ -1141,6 +1150,7 @@ __device__ __forceinline__ void sym_block_mixed(
             jw[jj] = jx;
             jw[TJ + jj] = jy;
             jw[2 * TJ + jj] = jz;
+            lds_step_fence();
           }
         }
       }

@@ -199,3 +199,30 @@ def test_kappa_reported():
     ps = synth.config(1, n=256)
     S, kap = oracle.forces(ps.pos, ps.mass, ps.soft, want_kappa=True)
     assert np.all(kap >= 1.0 - 1e-12)
+
+
+def test_kappa_closed_form():
+    # kappa_i = |(sum_j |t_jx|, sum_j |t_jy|, sum_j |t_jz|)| / |S_i| with
+    # t_j = m_j (x_j - x_i) / r^3 (Newtonian pairs).  Particle 0 at the
+    # origin, unit masses at (3, 0, 0), (0, 4, 0) and (-1, 0, 0):
+    # t = (1/9, 0, 0), (0, 1/16, 0), (-1, 0, 0), so S = (-8/9, 1/16, 0) and
+    # the absolute sums are (10/9, 1/16, 0).  Summing norms of the terms
+    # instead (1/9 + 1/16 + 1), or dropping the absolute value, gives other
+    # numbers.
+    pos = np.array([[0.0, 3.0, 0.0, -1.0], [0.0, 0.0, 4.0, 0.0],
+                    [0.0, 0.0, 0.0, 0.0]])
+    mass = np.ones(4)
+    soft = np.full(4, 1e-3)
+    S, kap = oracle.forces(pos, mass, soft, idx=np.array([0]), want_kappa=True)
+    np.testing.assert_allclose(S[:, 0], [-8.0 / 9.0, 1.0 / 16.0, 0.0], rtol=1e-15)
+    expected = math.hypot(10.0 / 9.0, 1.0 / 16.0) / math.hypot(8.0 / 9.0, 1.0 / 16.0)
+    assert kap[0] == pytest.approx(expected, rel=1e-14)
+    # terms of one sign per component: kappa = 1 exactly
+    S, kap = oracle.forces(pos[:, :3], mass[:3], soft[:3], idx=np.array([0]),
+                           want_kappa=True)
+    assert kap[0] == pytest.approx(1.0, rel=1e-15)
+    # midway between two equal masses the pulls cancel: S = 0, kappa = inf
+    pos2 = np.array([[-2.0, 0.0, 2.0], [0.0, 0.0, 0.0], [0.0, 0.0, 0.0]])
+    S, kap = oracle.forces(pos2, np.ones(3), np.full(3, 1e-3),
+                           idx=np.array([1]), want_kappa=True)
+    assert np.all(S[:, 0] == 0.0) and math.isinf(kap[0])
