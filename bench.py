@@ -1,29 +1,37 @@
 """Benchmark of the StePS direct-summation hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 2]
-                    [--no-cpu-baseline] [--no-modes]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 3]
+                    [--no-cpu-baseline] [--no-modes] [--no-batch] [--no-glass]
 
 A step is one comoving KDK step (kick + drift, one O(N^2) pair sum, kick) of
-the whole particle set, with state resident in HBM.  Default workload:
-N = 2^18 stereographically projected particles, D = 200 Mpc,
-r_max = 2000 Mpc, LCDM (0.3089 / 0.6911 / 67.74), FP64, stepping along its
-200-step log-uniform grid from a = 0.02.  The value is ordered pair
-interactions per second over the timed steps (N^2 per step).
+the whole particle set, with state resident in HBM.  Default workload
+(workload 3): N = 2^21 stereographically projected particles, D = 300 Mpc,
+r_max = 3000 Mpc, LCDM (0.3089 / 0.6911 / 67.74), sigma 1%, Zel'dovich
+velocities, FP64, stepping along a log-uniform grid from a = 0.02 (200 steps
+to a = 1, the step of workload 2).  The value is ordered pair interactions
+per second over the timed steps, N^2 per step: an ordered-pair equivalent,
+since the default kernels evaluate each unordered pair once for both
+particles; N(N - 1) per step is reported beside it.
 
 Also reported on the same JSON line:
   roofline     -- force kernel: 20 flop per ordered pair (convention) over
                   its average launch time (HIP events on its own stream),
-                  against the FP64 peak 78.6 TFLOP/s ("bound": "mfma" for the
-                  matrix-core kernels, which share that pipe, else "alu");
+                  against the FP64 vector peak 78.6 TFLOP/s (FP64 vector and
+                  FP64 matrix-core instructions issue through one pipe on
+                  gfx950, whose peak that is), or the FP32 one in mixed mode;
   cpu_baseline -- the CPU FP64 oracle on a bounded seeded sample of i rows
-                  against all N j (rank 0 only);
+                  against all N j, on every host thread and on one;
   modes        -- force-kernel pair rate in FP64 and both mixed modes at the
-                  same N and at N = 2^21, with the relative force error
-                  against the oracle sample (median, max).
+                  same N, with the relative force error against the oracle
+                  on 65 536 sampled rows (median, max, binned);
+  workload2    -- the same step timing and modes table at N = 2^18;
+  config2_200  -- workload 2 as specified: all 200 KDK steps a 0.02 -> 1.0
+                  at N = 2^18, with energies and momentum at both ends;
+  batch, batch_small, glass, periodic -- the ensemble, glass-relaxation and
+                  periodic-box legs.
 
---workload 3 runs the three precision modes at N = 2^21 against the oracle
-on 65 536 sampled rows (about a minute of host time); --workload 5 runs
-N = 2^22 for 50 steps in mixed precision and in FP64 with the energy checks.
+--workload 2 makes workload 2 the headline; --workload 5 runs N = 2^22 for
+50 steps in mixed precision and in FP64 with the energy checks.
 """
 from __future__ import annotations
 
@@ -40,6 +48,7 @@ if ROOT not in sys.path:
 FP64_PEAK_TF = 78.6
 FP32_PEAK_TF = 157.3
 FLOP_PER_PAIR = 20
+METRIC = "pair interactions/s (ordered-pair equivalent, whole KDK step)"
 
 
 def parse():
@@ -47,21 +56,26 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", type=int, default=2, choices=[1, 2, 3, 5])
+    ap.add_argument("--workload", type=int, default=3, choices=[2, 3, 5])
     ap.add_argument("--no-glass", action="store_true",
-                    help="skip the glass-relaxation leg")
+                    help="skip the glass-relaxation and periodic legs")
     ap.add_argument("--li-study-only", action="store_true",
                     help="workload 5: only the Layzer-Irvine step-convergence "
                          "study at N = 2^17")
     ap.add_argument("--precision", default="fp64",
                     choices=["fp64", "mixed", "kahan"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the precision-mode tables and their oracle rows")
+    ap.add_argument("--oracle-rows", type=int, default=65536,
+                    help="oracle rows behind the headline's modes table")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the workload-2 and 200-step legs")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-member ensemble comparison")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target CPU time of the oracle sample")
+                    help="target CPU time of the single-thread oracle sample")
     ap.add_argument("--tile", default=None, metavar="R,TJ,JSPLIT,VARIANT",
                     help="force the force kernel's launch shape (a compiled "
                          "variant; JSPLIT 0 = the built-in split), e.g. "
@@ -74,6 +88,152 @@ def parse():
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kdk_grid(ps, workload):
+    """The step grid of a workload: its own log-uniform grid, or for
+    workload 3 (one evaluation per mode as specified) the 200-step grid
+    a 0.02 -> 1.0 of workload 2."""
+    import numpy as np
+    if workload != 3:
+        return ps.a_grid()
+    k = np.arange(201, dtype=np.float64)
+    g = ps.a0 * (1.0 / ps.a0) ** (k / 200)
+    g[-1] = 1.0
+    return g
+
+
+def kdk_leg(st, dev, ps, grid, steps, warmup, precision, tile=None,
+            workload=None):
+    """Times `steps` KDK steps after `warmup` untimed ones, from the set's
+    initial state along `grid`; returns the timing, the force kernel's
+    roofline and the final state."""
+    import torch
+    n = ps.n
+    c = ps.cosmo
+    cosmo = st.Cosmology(c.H0, c.omega_m, c.omega_l, c.omega_r)
+    stream = torch.cuda.current_stream()
+    ctx = st.Context(0, precision=precision, flags=st.STEPS_PROFILE,
+                     stream=stream)
+    if tile:
+        ctx.set_tile(*(int(x) for x in tile.split(",")))
+    pos, vel, mass, soft = dev(ps.pos), dev(ps.vel), dev(ps.mass), dev(ps.soft)
+    acc = st.steps_forces(pos, mass, soft, ctx=ctx)
+    if warmup + steps > len(grid) - 1:
+        raise SystemExit("at most %d steps on this grid" % (len(grid) - 1))
+    k = 0
+    for _ in range(warmup):
+        st.steps_step(pos, vel, mass, soft, acc, grid[k], grid[k + 1] - grid[k],
+                      cosmo, ctx=ctx)
+        k += 1
+    torch.cuda.synchronize()
+    ctx.force_timing(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.steps_step(pos, vel, mass, soft, acc, grid[k], grid[k + 1] - grid[k],
+                      cosmo, ctx=ctx)
+        k += 1
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    force_ms, force_cnt = ctx.force_timing(reset=True)
+    t = ctx.get_tile(n)
+    ctx.close()
+    assert bool(torch.isfinite(pos).all()) and bool(torch.isfinite(acc).all())
+    pairs = float(n) * n
+    kern_ms = force_ms / max(1, force_cnt)
+    achieved = FLOP_PER_PAIR * pairs / (kern_ms * 1e-3) / 1e12
+    peak = FP64_PEAK_TF if precision == "fp64" else FP32_PEAK_TF
+    log("n=%d %s: %d steps, %.2f ms/step, %.3e pairs/s; force kernel %.2f ms "
+        "(%d launches), %.3f of peak"
+        % (n, precision, steps, 1e3 * elapsed / steps, pairs * steps / elapsed,
+           kern_ms, force_cnt, achieved / peak))
+    name = force_kernel_name(precision, t)
+    return {
+        "n": n, "steps": steps, "warmup": warmup,
+        "a_range": [float(grid[warmup]), float(grid[warmup + steps])],
+        "ms_per_step": 1e3 * elapsed / steps,
+        "pairs_per_s": pairs * steps / elapsed,
+        "pairs_distinct_per_s": float(n) * (n - 1) * steps / elapsed,
+        "tile": t,
+        "roofline": {
+            # the FP64 kernels (vector or matrix-core) are priced at the FP64
+            # vector peak: on gfx950 FP64 vector and FP64 matrix-core
+            # instructions issue through the one FP64 pipe with that peak
+            "bound": "alu", "pipe": "fp64" if precision == "fp64" else "fp32",
+            "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": profiled_traffic(precision, t, workload),
+            "kernel": name, "kernel_ms": kern_ms,
+            "kernel_launches": force_cnt,
+            "flop_per_pair": FLOP_PER_PAIR,
+            "pair_convention": "N^2 ordered pairs per evaluation (ordered-pair "
+                               "equivalent: the symmetric kernels evaluate "
+                               "N(N-1)/2 unordered pairs)"},
+    }, (pos, vel, acc)
+
+
+def oracle_rows(ps, rows, seed, chunk=8192, first_timed=0):
+    """The oracle's S and kappa on `rows` seeded-sampled i of the set (all j),
+    in chunks of `chunk` rows on every host thread.  Returns ((idx, S,
+    kappa), timing) where timing covers the first `first_timed` rows."""
+    import numpy as np
+    import oracle
+    idx = np.sort(np.random.default_rng(seed).choice(ps.n, rows, replace=False))
+    refs, kaps = [], []
+    t0 = time.perf_counter()
+    timed = None
+    for k in range(0, rows, chunk):
+        r, kp = oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx[k:k + chunk],
+                              want_kappa=True)
+        refs.append(r)
+        kaps.append(kp)
+        done = min(rows, k + chunk)
+        if timed is None and first_timed and done >= first_timed:
+            timed = (done, time.perf_counter() - t0)
+        log("oracle rows %d/%d (%.0f s)" % (done, rows, time.perf_counter() - t0))
+    return (idx, np.concatenate(refs, axis=1), np.concatenate(kaps)), timed
+
+
+def cpu_baseline(ps, timed, seconds):
+    """The oracle's pair rate on every host thread (from the first chunks of
+    the parity rows, `timed` = (rows, seconds)) and on one thread (a
+    bounded sample of about `seconds`), with the extrapolated time of one
+    full evaluation."""
+    import numpy as np
+    import oracle
+    n = ps.n
+    rng = np.random.default_rng(12345)
+    probe = rng.choice(n, 64, replace=False)
+    t = time.perf_counter()
+    oracle.forces(ps.pos, ps.mass, ps.soft, idx=probe, nthreads=1)
+    rate1 = 64 * n / (time.perf_counter() - t)
+    m1 = int(min(n, max(64, rate1 * seconds / n)))
+    idx1 = np.sort(rng.choice(n, m1, replace=False))
+    t = time.perf_counter()
+    oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx1, nthreads=1)
+    dt1 = time.perf_counter() - t
+    single = m1 * float(n) / dt1
+    if timed is None:
+        m = int(min(n, max(256, 8 * m1)))
+        idx = np.sort(rng.choice(n, m, replace=False))
+        t = time.perf_counter()
+        oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx)
+        timed = (m, time.perf_counter() - t)
+    rows, dt = timed
+    value = rows * float(n) / dt
+    log("cpu baseline: %.3e pairs/s on %d threads, %.3e on one"
+        % (value, oracle.num_threads(), single))
+    return {"value": value, "unit": "pairs/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "FP64 oracle pair sums for %d seeded-sampled i of the "
+                      "N=%d set against all j (%.1f s)" % (rows, n, dt),
+            "single_thread": {"value": single, "unit": "pairs/s", "cores": 1,
+                              "sample": "%d seeded-sampled i against all j "
+                                        "(%.1f s)" % (m1, dt1)},
+            "extrapolated_full_evaluation_s": float(n) * n / value,
+            "extrapolated_full_evaluation_s_single_thread": float(n) * n / single,
+            "note": "extrapolated from the sampled rows: every row costs N "
+                    "pair terms"}
 
 
 def main():
@@ -99,120 +259,55 @@ def main():
     if args.workload == 5:
         print(json.dumps(workload5(st, dev, args)), flush=True)
         return
-    if args.workload == 3:
-        print(json.dumps(workload3(st, dev, args)), flush=True)
-        return
 
     ps = synth.config(args.workload)
     n = ps.n
+    grid = kdk_grid(ps, args.workload)
     log("workload %d: n=%d precision=%s" % (args.workload, n, args.precision))
-    grid = ps.a_grid()
-    c = ps.cosmo
-    cosmo = st.Cosmology(c.H0, c.omega_m, c.omega_l, c.omega_r)
-    stream = torch.cuda.current_stream()
-    ctx = st.Context(0, precision=args.precision, flags=st.STEPS_PROFILE,
-                     stream=stream)
-    if args.tile:
-        ctx.set_tile(*(int(x) for x in args.tile.split(",")))
-    pos, vel, mass, soft = dev(ps.pos), dev(ps.vel), dev(ps.mass), dev(ps.soft)
-    acc = st.steps_forces(pos, mass, soft, ctx=ctx)
-
-    total = args.warmup + args.steps
-    if total > len(grid) - 1:
-        raise SystemExit("at most %d steps on this grid" % (len(grid) - 1))
-    k = 0
-    for _ in range(args.warmup):
-        st.steps_step(pos, vel, mass, soft, acc, grid[k], grid[k + 1] - grid[k],
-                      cosmo, ctx=ctx)
-        k += 1
-    torch.cuda.synchronize()
-    ctx.force_timing(reset=True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st.steps_step(pos, vel, mass, soft, acc, grid[k], grid[k + 1] - grid[k],
-                      cosmo, ctx=ctx)
-        k += 1
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    force_ms, force_cnt = ctx.force_timing(reset=True)
-    elapsed = t1 - t0
-    ms_step = 1e3 * elapsed / args.steps
-    pairs = float(n) * n
-    value = pairs * args.steps / elapsed
-    kern_ms = force_ms / max(1, force_cnt)
-    achieved = FLOP_PER_PAIR * pairs / (kern_ms * 1e-3) / 1e12
-    peak = FP64_PEAK_TF if args.precision == "fp64" else FP32_PEAK_TF
-    tile = ctx.get_tile(n)
-    log("%d steps: %.2f ms/step, %.3e pairs/s; force kernel %.2f ms (%d launches)"
-        % (args.steps, ms_step, value, kern_ms, force_cnt))
-    assert bool(torch.isfinite(pos).all()) and bool(torch.isfinite(acc).all())
-
-    traffic = profiled_traffic(args.precision, tile, args.workload)
+    leg, _ = kdk_leg(st, dev, ps, grid, args.steps, args.warmup,
+                     args.precision, args.tile, args.workload)
     out = {
-        "metric": "pair interactions/s (ordered pairs, whole KDK step)",
-        "value": value,
+        "metric": METRIC,
+        "value": leg["pairs_per_s"],
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32-pair/f64-acc",
         "data": "synthetic",
-        "config": {"workload": "stereographic sphere N=%d D=%g r_max=%g, %s, "
-                               "KDK from a=%.3f" % (n, ps.params["D"],
-                                                    ps.params["r_max"],
-                                                    args.precision, grid[0]),
-                   "n": n, "precision": args.precision, "tile": tile,
+        "config": {"workload": "stereographic sphere N=%d D=%g r_max=%g LCDM, "
+                               "%s, KDK steps a %.4f -> %.4f"
+                               % (n, ps.params["D"], ps.params["r_max"],
+                                  args.precision, leg["a_range"][0],
+                                  leg["a_range"][1]),
+                   "n": n, "precision": args.precision, "tile": leg["tile"],
                    "parallelism": "single GPU"},
-        # the FP64 matrix-core kernel and the vector kernels are both priced
-        # at the FP64 peak: on gfx950 dense FP64 MFMA and FP64 VALU share one
-        # 78.6 TFLOP/s pipe
-        "roofline": {"bound": "mfma" if tile["variant"] & 4
-                     and args.precision == "fp64" else "alu",
-                     "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": traffic,
-                     "kernel": force_kernel_name(args.precision, tile),
-                     "kernel_ms": kern_ms,
-                     "flop_per_pair": FLOP_PER_PAIR},
+        "pairs_distinct_per_s": leg["pairs_distinct_per_s"],
+        "roofline": leg["roofline"],
     }
 
-    sample_rows = big_rows = None
-    big = None if args.no_modes else synth.config(3)
-    if not args.no_cpu_baseline:
-        import oracle
-        rng = np.random.default_rng(12345)
-        oracle.forces(ps.pos, ps.mass, ps.soft, idx=rng.choice(n, 16, replace=False))
-        probe = rng.choice(n, 512, replace=False)
-        t = time.perf_counter()
-        oracle.forces(ps.pos, ps.mass, ps.soft, idx=probe)
-        rate = 512 * n / (time.perf_counter() - t)
-        m = int(min(n, max(64, rate * args.cpu_seconds / n)))
-        idx = np.sort(rng.choice(n, m, replace=False))
-        log("cpu baseline: oracle on %d sampled rows (%d threads)" % (m, oracle.num_threads()))
-        # the same positions the GPU starts from (before stepping)
-        t = time.perf_counter()
-        ref, kap = oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx, want_kappa=True)
-        dt = time.perf_counter() - t
-        sample_rows = (idx, ref, kap)
-        out["cpu_baseline"] = {
-            "value": m * float(n) / dt, "unit": "pairs/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "FP64 oracle pair sums for %d seeded-sampled i of the "
-                      "N=%d set against all j (%.1f s)" % (m, n, dt)}
-        if not args.no_modes:
-            # the oracle's rows of the 2^21 set, the reference of its modes
-            # table (not part of the timed sample above)
-            bidx = np.sort(np.random.default_rng(3).choice(big.n, 32, replace=False))
-            big_rows = (bidx,) + oracle.forces(big.pos, big.mass, big.soft, idx=bidx,
-                                               want_kappa=True)
-
+    rows, timed = None, None
     if not args.no_modes:
-        out["modes"] = mode_table(st, ps, sample_rows, dev)
-        out["modes_n2e21"] = mode_table(st, big, big_rows, dev)
+        rows, timed = oracle_rows(ps, args.oracle_rows, seed=33,
+                                  first_timed=16384)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(ps, timed, args.cpu_seconds)
+    if not args.no_modes:
+        out["modes"] = mode_table(st, ps, rows, dev, reps=3)
+    if not args.no_extras and args.workload == 3:
+        w2 = synth.config(2)
+        leg2, _ = kdk_leg(st, dev, w2, w2.a_grid(), 20, 3, "fp64", None, 2)
+        w2rows = None
+        if not args.no_modes:
+            w2rows, _ = oracle_rows(w2, 4096, seed=22)
+        leg2["modes"] = mode_table(st, w2, w2rows, dev, reps=3)
+        out["workload2"] = leg2
+    if not args.no_extras:
+        out["config2_200"] = config2_full(st, dev)
     if not args.no_batch:
         out["batch"] = batch_leg(st, dev, args.batch_steps)
         # many small members (N_b ~ 256 ... 4096): where one launch per
@@ -222,7 +317,6 @@ def main():
     if not args.no_glass:
         out["glass"] = glass_leg(st, dev)
         out["periodic"] = periodic_leg(st, dev)
-    ctx.close()
     if args.copy_calibration:
         nb = args.copy_calibration << 20
         src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
@@ -233,6 +327,46 @@ def main():
         log("copy calibration: %d MiB read + %d MiB written" % (
             args.copy_calibration, args.copy_calibration))
     print(json.dumps(out), flush=True)
+
+
+def config2_full(st, dev):
+    """Workload 2 as specified: N = 2^18, all 200 log-uniform KDK steps
+    a 0.02 -> 1.0, FP64.  Whole-run pair rate; energies (K, W) at both ends;
+    the pair-force momentum |sum m S| / sum |m S| at the end (zero up to
+    rounding by Newton's third law) and the peculiar momentum."""
+    import numpy as np
+    import torch
+    import synth
+    ps = synth.config(2)
+    n, grid, c = ps.n, ps.a_grid(), ps.cosmo
+    cosmo = st.Cosmology(c.H0, c.omega_m, c.omega_l, c.omega_r)
+    ctx = st.Context(0, precision="fp64")
+    p, v, m, h = dev(ps.pos), dev(ps.vel), dev(ps.mass), dev(ps.soft)
+    acc = st.steps_forces(p, m, h, ctx=ctx)
+    e0 = st.steps_energy(p, v, m, h, grid[0], cosmo, ctx=ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(len(grid) - 1):
+        st.steps_step(p, v, m, h, acc, grid[k], grid[k + 1] - grid[k], cosmo,
+                      ctx=ctx)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    e1 = st.steps_energy(p, v, m, h, grid[-1], cosmo, ctx=ctx)
+    ctx.close()
+    ms = (m[None, :] * acc).cpu().numpy()
+    pair_p = float(np.linalg.norm(ms.sum(axis=1)) / np.abs(ms).sum())
+    steps = len(grid) - 1
+    out = {"n": n, "steps": steps, "a_range": [float(grid[0]), float(grid[-1])],
+           "seconds": elapsed, "ms_per_step": 1e3 * elapsed / steps,
+           "pairs_per_s": float(n) * n * steps / elapsed,
+           "start": {"a": float(grid[0]), "K": e0["K"], "W": e0["W"], "P": e0["P"]},
+           "end": {"a": float(grid[-1]), "K": e1["K"], "W": e1["W"], "P": e1["P"]},
+           "pair_momentum_rel_end": pair_p,
+           "finite": bool(torch.isfinite(p).all()) and bool(torch.isfinite(v).all())}
+    log("workload 2, 200 steps: %.2f s (%.3e pairs/s); K %.4e -> %.4e, "
+        "W %.4e -> %.4e; |sum m S|/sum|m S| %.2e"
+        % (elapsed, out["pairs_per_s"], e0["K"], e1["K"], e0["W"], e1["W"], pair_p))
+    return out
 
 
 def force_kernel_name(precision, tile):
@@ -599,90 +733,77 @@ def binned_errors(err, kappa, radius, nbins=3):
     return out
 
 
-def workload3(st, dev, args, rows=65536):
-    """Workload 3: N = 2^21, one force evaluation per precision mode (FP64,
-    FP32 pairs with FP64 accumulation, FP32 pairs with Kahan accumulation),
-    each against the FP64 oracle on `rows` seeded-sampled i (all j), with
-    pair-interactions/s and the mixed-to-FP64 ratio."""
-    import numpy as np
-    import oracle
-    import synth
-    ps = synth.config(3)
-    n = ps.n
-    log("workload 3: n=%d, oracle on %d sampled rows (%d threads)"
-        % (n, rows, oracle.num_threads()))
-    idx = np.sort(np.random.default_rng(33).choice(n, rows, replace=False))
-    refs, kaps = [], []
-    t0 = time.perf_counter()
-    step = 8192
-    for k in range(0, rows, step):
-        r, kp = oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx[k:k + step],
-                              want_kappa=True)
-        refs.append(r)
-        kaps.append(kp)
-        log("oracle rows %d/%d (%.0f s)" % (min(rows, k + step), rows,
-                                            time.perf_counter() - t0))
-    odt = time.perf_counter() - t0
-    sample = (idx, np.concatenate(refs, axis=1), np.concatenate(kaps))
-    modes = mode_table(st, ps, sample, dev)
-    return {
-        "metric": "pair interactions/s (ordered pairs, one force evaluation)",
-        "value": modes["fp64"]["pairs_per_s"],
-        "unit": "pairs/s",
-        "n_gpus": 1,
-        "higher_is_better": True,
-        "data": "synthetic",
-        "config": {"workload": "stereographic sphere N=%d D=%g r_max=%g, "
-                               "three precision modes" % (n, ps.params["D"],
-                                                          ps.params["r_max"]),
-                   "n": n, "parallelism": "single GPU"},
-        "modes": modes,
-        "cpu_baseline": {"value": float(rows) * n / odt, "unit": "pairs/s",
-                         "cores": oracle.num_threads(), "kind": "oracle",
-                         "sample": "FP64 oracle pair sums for %d seeded-sampled "
-                                   "i against all %d j (%.1f s)" % (rows, n, odt)},
-    }
-
-
-def mode_table(st, ps, rows, dev):
-    """Force-kernel rate per precision mode at this N, one timed launch after
-    one warm-up, and the error against the oracle rows if given."""
+def _mode_entry(st, ps, rows, dev, reps, prec, tile=None):
+    """One row of the modes table: mean kernel time of `reps` launches after
+    one warm-up in precision prec (optionally a forced launch shape), and the
+    error against the oracle rows if given."""
     import numpy as np
     import torch
     n = ps.n
     pos, mass, soft = dev(ps.pos), dev(ps.mass), dev(ps.soft)
+    ctx = st.Context(0, precision=prec, flags=st.STEPS_PROFILE)
+    if tile is not None:
+        ctx.set_tile(*tile)
+    acc = st.steps_forces(pos, mass, soft, ctx=ctx)
+    torch.cuda.synchronize()
+    ctx.force_timing(reset=True)
+    for _ in range(reps):
+        st.steps_forces(pos, mass, soft, acc=acc, ctx=ctx)
+    ms, cnt = ctx.force_timing(reset=True)
+    kms = ms / cnt
+    rate = float(n) * n / (kms * 1e-3)
+    peak = FP64_PEAK_TF if prec == "fp64" else FP32_PEAK_TF
+    entry = {"kernel_ms": kms, "launches": cnt, "pairs_per_s": rate,
+             "pairs_distinct_per_s": float(n) * (n - 1) / (kms * 1e-3),
+             "tflops_20": FLOP_PER_PAIR * rate / 1e12,
+             "frac_peak": FLOP_PER_PAIR * rate / 1e12 / peak,
+             "tile": ctx.get_tile(n)}
+    if rows is not None:
+        idx, ref, kap = rows
+        got = acc.cpu().numpy()[:, idx]
+        err = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        entry["rel_err_median"] = float(np.median(err))
+        entry["rel_err_max"] = float(err.max())
+        entry["rel_err_rows"] = int(idx.size)
+        entry["rel_err_binned"] = binned_errors(err, kap, np.linalg.norm(ps.pos[:, idx], axis=0))
+    ctx.close()
+    return entry
+
+
+def mode_table(st, ps, rows, dev, reps=3, refine=True):
+    """Force-kernel rate per precision mode at this N (mean of `reps` timed
+    launches after one warm-up), and the error against the oracle rows if
+    given; with refine, also the default mixed shape with one Newton step on
+    the FP32 r^-3."""
+    n = ps.n
     res = {}
     for prec in ("fp64", "mixed", "kahan"):
-        ctx = st.Context(0, precision=prec, flags=st.STEPS_PROFILE)
-        acc = st.steps_forces(pos, mass, soft, ctx=ctx)
-        torch.cuda.synchronize()
-        ctx.force_timing(reset=True)
-        reps = 3 if n <= 300000 else 1
-        for _ in range(reps):
-            st.steps_forces(pos, mass, soft, acc=acc, ctx=ctx)
-        ms, cnt = ctx.force_timing(reset=True)
-        kms = ms / cnt
-        rate = float(n) * n / (kms * 1e-3)
-        peak = FP64_PEAK_TF if prec == "fp64" else FP32_PEAK_TF
-        entry = {"kernel_ms": kms, "pairs_per_s": rate,
-                 "tflops_20": FLOP_PER_PAIR * rate / 1e12,
-                 "frac_peak": FLOP_PER_PAIR * rate / 1e12 / peak,
-                 "tile": ctx.get_tile(n)}
-        if rows is not None:
-            idx, ref, kap = rows
-            got = acc.cpu().numpy()[:, idx]
-            err = np.linalg.norm(got - ref, axis=0) / np.linalg.norm(ref, axis=0)
-            entry["rel_err_median"] = float(np.median(err))
-            entry["rel_err_max"] = float(err.max())
-            entry["rel_err_rows"] = int(idx.size)
-            entry["rel_err_binned"] = binned_errors(err, kap, np.linalg.norm(ps.pos[:, idx], axis=0))
+        entry = _mode_entry(st, ps, rows, dev, reps, prec)
         res[prec] = entry
         log("n=%d %s: %.2f ms, %.3e pairs/s%s" % (
-            n, prec, kms, rate,
+            n, prec, entry["kernel_ms"], entry["pairs_per_s"],
             "" if rows is None else ", err median %.2e max %.2e" % (
                 entry["rel_err_median"], entry["rel_err_max"])))
-        ctx.close()
     res["mixed_speedup_vs_fp64"] = res["mixed"]["pairs_per_s"] / res["fp64"]["pairs_per_s"]
+    if refine:
+        # the one-sided FP64 kernel on the vector ALU alone (variant 3, no
+        # matrix cores) beside the default
+        res["fp64_valu"] = _mode_entry(st, ps, rows, dev, reps, "fp64",
+                                       (4, 128, 0, 3))
+        log("n=%d fp64 vector-ALU kernel: %.2f ms, %.3e pairs/s, %.3f of peak"
+            % (n, res["fp64_valu"]["kernel_ms"], res["fp64_valu"]["pairs_per_s"],
+               res["fp64_valu"]["frac_peak"]))
+        # the default mixed shape with one Newton step on the FP32 r^-3
+        # (variant 26 beside the default's variant 10)
+        t = res["mixed"]["tile"]
+        if t["variant"] == 10:
+            res["mixed_newton"] = _mode_entry(st, ps, rows, dev, reps, "mixed",
+                                              (t["r"], t["tj"], t["jsplit"], 26))
+            log("n=%d mixed with Newton step: %.2f ms, %.3e pairs/s%s" % (
+                n, res["mixed_newton"]["kernel_ms"], res["mixed_newton"]["pairs_per_s"],
+                "" if rows is None else ", err median %.2e max %.2e" % (
+                    res["mixed_newton"]["rel_err_median"],
+                    res["mixed_newton"]["rel_err_max"])))
     return res
 
 

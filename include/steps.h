@@ -375,7 +375,10 @@ int steps_batch_run(steps_ctx *ctx, const steps_batch *batch,
  * its r, tj and variant must name an ensemble kernel of the precision, else
  * STEPS_E_INVAL, and STEPS_BATCH_AUTOTUNE then has no choice to make), or
  * the fastest one under STEPS_BATCH_AUTOTUNE, or a default.
- * Launch shape of the last steps_batch_run on this context: */
+ * Launch shape of the last steps_batch_run on this context (r, tj and
+ * variant of its kernel; jsplit = the largest number of parts a member's
+ * j-range was cut into, 1 when every work item covers its member's whole
+ * j-range): */
 int steps_batch_tile(steps_ctx *ctx, steps_tile *out);
 
 /* ---- background helpers (host only, no device work) ------------------- */

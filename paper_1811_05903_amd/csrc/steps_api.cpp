@@ -123,8 +123,7 @@ int ensure(steps_ctx *c, Buffer &b, size_t bytes, const char *what) {
 
 // A caller array must be device (or managed) memory on the context device,
 // with at least `bytes` bytes from p to the end of its allocation.
-int check_ptr(const steps_ctx *c, const void *p, size_t bytes,
-              const char *name) {
+int check_ptr_dev(int device, const void *p, size_t bytes, const char *name) {
   if (!p) return fail(STEPS_E_INVAL, "%s is NULL", name);
   hipPointerAttribute_t at;
   hipError_t e = hipPointerGetAttributes(&at, p);
@@ -136,9 +135,9 @@ int check_ptr(const steps_ctx *c, const void *p, size_t bytes,
       !at.isManaged) {
     return fail(STEPS_E_INVAL, "%s (%p) is not device memory", name, p);
   }
-  if (at.type == hipMemoryTypeDevice && at.device != c->device) {
-    return fail(STEPS_E_INVAL, "%s is on device %d, the context on device %d",
-                name, at.device, c->device);
+  if (at.type == hipMemoryTypeDevice && at.device != device) {
+    return fail(STEPS_E_INVAL, "%s is on device %d, the call runs on device %d",
+                name, at.device, device);
   }
   hipDeviceptr_t base = nullptr;
   size_t size = 0;
@@ -155,6 +154,11 @@ int check_ptr(const steps_ctx *c, const void *p, size_t bytes,
     (void)hipGetLastError();
   }
   return STEPS_OK;
+}
+
+int check_ptr(const steps_ctx *c, const void *p, size_t bytes,
+              const char *name) {
+  return check_ptr_dev(c->device, p, bytes, name);
 }
 
 bool overlap(const void *a, size_t na, const void *b, size_t nb) {
@@ -527,7 +531,7 @@ int reserve_forces(steps_ctx *c, int n, steps_tile *t) {
   *t = choose_tile(c, n);
   int rc = run_forces_tile(c, nullptr, nullptr, nullptr, n, nullptr, *t, false);
   if (rc == STEPS_E_NOMEM && (t->variant & steps::kVarSym) && !c->tile_forced) {
-    t->variant &= ~steps::kVarSym;
+    t->variant &= ~(steps::kVarSym | steps::kVarQuad);
     t->jsplit = heuristic_jsplit(prec_class(c->precision), n, t->r, t->tj,
                                  t->variant);
     rc = run_forces_tile(c, nullptr, nullptr, nullptr, n, nullptr, *t, false);
@@ -656,22 +660,29 @@ steps::Background make_background(const steps_cosmology *k) {
                            k->mode == STEPS_COMOVING_PERIODIC);
 }
 
-int check_force_args(steps_ctx *c, const double *pos, const double *mass,
-                     const double *soft, int64_t n, const void *out,
-                     size_t out_bytes, const char *out_name) {
+int check_force_args_dev(int device, const double *pos, const double *mass,
+                         const double *soft, int64_t n, const void *out,
+                         size_t out_bytes, const char *out_name) {
   int rc = check_n(n);
   if (rc) return rc;
   if (n == 0) return STEPS_OK;
   const size_t v3 = 3 * (size_t)n * sizeof(double), v1 = (size_t)n * sizeof(double);
-  if ((rc = check_ptr(c, pos, v3, "pos"))) return rc;
-  if ((rc = check_ptr(c, mass, v1, "mass"))) return rc;
-  if ((rc = check_ptr(c, soft, v1, "soft"))) return rc;
-  if ((rc = check_ptr(c, out, out_bytes, out_name))) return rc;
+  if ((rc = check_ptr_dev(device, pos, v3, "pos"))) return rc;
+  if ((rc = check_ptr_dev(device, mass, v1, "mass"))) return rc;
+  if ((rc = check_ptr_dev(device, soft, v1, "soft"))) return rc;
+  if ((rc = check_ptr_dev(device, out, out_bytes, out_name))) return rc;
   if (overlap(out, out_bytes, pos, v3) || overlap(out, out_bytes, mass, v1) ||
       overlap(out, out_bytes, soft, v1)) {
     return fail(STEPS_E_INVAL, "%s overlaps an input array", out_name);
   }
   return STEPS_OK;
+}
+
+int check_force_args(steps_ctx *c, const double *pos, const double *mass,
+                     const double *soft, int64_t n, const void *out,
+                     size_t out_bytes, const char *out_name) {
+  return check_force_args_dev(c->device, pos, mass, soft, n, out, out_bytes,
+                              out_name);
 }
 
 }  // namespace
@@ -1366,14 +1377,36 @@ struct BatchLayout {
   std::vector<int> tile_beg, tile_end;   // member-local tiles, slot ranges
   std::vector<int4> items;               // (i0, iend, jbeg, jend)
   std::vector<int> tbase;                // first tile of the item's j-range
-  std::vector<int> islot;                // j-chunk (output plane) of the item
+  std::vector<int> islot;                // j-chunk (output plane) of the item,
+                                         // or the unit's slot (symmetric)
   std::vector<int> kc;                   // j-chunks of each member
   int planes = 1;                        // largest kc
+  // symmetric kernels: items are the chunk-pair units of every member
+  bool sym = false;
+  int chunk = 0;                         // particles per chunk
+  std::vector<int> moff, mq, mubase;     // per member: start, chunks, slot base
+  int64_t nslots = 0;
 };
 
 // Work items the persistent ensemble kernel should have to spread evenly
 // over the GPU: a few per resident block.
 constexpr int64_t kBatchTargetItems = 8192;
+
+// Chunk size of the symmetric ensemble kernels: the smallest of 1024,
+// 2048, ... whose unit slots (72 chunk bytes per unit, Q (Q + 1) / 2 units
+// for a member of Q chunks) fit in 8 GiB.
+int batch_sym_chunk(const std::vector<int> &soff) {
+  const double cap = 8.0 * (1ull << 30);
+  int c = 1024;
+  for (;; c *= 2) {
+    double slots = 0.0;
+    for (size_t a = 0; a + 1 < soff.size(); ++a) {
+      const double q = (double)((soff[a + 1] - soff[a] + c - 1) / c);
+      slots += q * (q + 1) / 2;
+    }
+    if (slots * 72.0 * c <= cap || c >= (1 << 20)) return c;
+  }
+}
 
 // Tiles of tj slots from each member's start; items of 256 r slots.  When
 // the ensemble gives fewer than kBatchTargetItems such blocks, each member's
@@ -1382,7 +1415,14 @@ constexpr int64_t kBatchTargetItems = 8192;
 // (i-block, j-chunk) and writes its own output plane, the planes being
 // summed in order afterwards.  Items are ordered by member size (the cost of
 // an item), largest first.
-BatchLayout batch_layout(const std::vector<int> &soff, int r, int tj) {
+//
+// Symmetric kernels instead cut each member into chunks of batch_sym_chunk
+// particles (multiples of tj from the member's start) and take one item per
+// unit (R, s), R <= s, of chunk pairs, members largest first, off-diagonal
+// units of a member before its diagonal ones.  Unit (R, s) of member a
+// writes slot mubase[a] + s (s + 1) / 2 + R.
+BatchLayout batch_layout(const std::vector<int> &soff, int r, int tj,
+                         bool sym) {
   BatchLayout L;
   const int A = (int)soff.size() - 1;
   std::vector<int> mtb(A);
@@ -1395,6 +1435,40 @@ BatchLayout batch_layout(const std::vector<int> &soff, int r, int tj) {
     }
     blocks += (soff[a + 1] - soff[a] + 256LL * r - 1) / (256LL * r);
   }
+  std::vector<int> order(A);
+  for (int a = 0; a < A; ++a) order[a] = a;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return soff[x + 1] - soff[x] > soff[y + 1] - soff[y];
+  });
+  if (sym) {
+    L.sym = true;
+    L.chunk = batch_sym_chunk(soff);
+    const int C = L.chunk;
+    L.kc.assign(A, 1);
+    L.moff.assign(soff.begin(), soff.end() - 1);
+    L.mq.assign(A, 0);
+    L.mubase.assign(A, 0);
+    for (int a = 0; a < A; ++a) {
+      L.mq[a] = (soff[a + 1] - soff[a] + C - 1) / C;
+      L.mubase[a] = (int)L.nslots;
+      L.nslots += (int64_t)L.mq[a] * (L.mq[a] + 1) / 2;
+    }
+    for (int a : order) {
+      const int q = L.mq[a], o = soff[a], e = soff[a + 1];
+      for (int pass = 0; pass < 2; ++pass) {  // off-diagonal, then diagonal
+        for (int cs = 0; cs < q; ++cs) {
+          for (int cr = 0; cr <= cs; ++cr) {
+            if ((cr == cs) != (pass == 1)) continue;
+            L.items.push_back(make_int4(o + cr * C, std::min(e, o + (cr + 1) * C),
+                                        o + cs * C, std::min(e, o + (cs + 1) * C)));
+            L.tbase.push_back(mtb[a] + cs * (C / tj));
+            L.islot.push_back(L.mubase[a] + cs * (cs + 1) / 2 + cr);
+          }
+        }
+      }
+    }
+    return L;
+  }
   const int K = (int)std::min<int64_t>(
       64, std::max<int64_t>(1, (kBatchTargetItems + blocks - 1) / std::max<int64_t>(1, blocks)));
   L.kc.assign(A, 1);
@@ -1406,11 +1480,6 @@ BatchLayout batch_layout(const std::vector<int> &soff, int r, int tj) {
     L.kc[a] = std::max(1, (ntl + per[a] - 1) / per[a]);  // all non-empty
     L.planes = std::max(L.planes, L.kc[a]);
   }
-  std::vector<int> order(A);
-  for (int a = 0; a < A; ++a) order[a] = a;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    return soff[x + 1] - soff[x] > soff[y + 1] - soff[y];
-  });
   for (int a : order) {
     for (int i0 = soff[a]; i0 < soff[a + 1]; i0 += 256 * r) {
       const int iend = std::min(i0 + 256 * r, soff[a + 1]);
@@ -1424,6 +1493,10 @@ BatchLayout batch_layout(const std::vector<int> &soff, int r, int tj) {
     }
   }
   return L;
+}
+
+bool batch_is_sym(const steps::BatchVariant *v) {
+  return (v->variant & steps::kVarSym) != 0;
 }
 
 // Everything one ensemble run keeps on the device (carved from the arena).
@@ -1441,6 +1514,8 @@ struct BatchDev {
   int4 *items;
   int *islot, *kc;
   double *part;  // [planes][3][N] j-chunk partials (planes > 1)
+  double *usum;  // symmetric kernels: [slots][9][chunk] unit sums
+  int *moff, *mq, *mubase;  // symmetric kernels: per-member layout
 };
 
 struct BatchRun {
@@ -1450,6 +1525,8 @@ struct BatchRun {
   BatchDev d;
   const steps::BatchVariant *v = nullptr;
   int ntiles = 0, nitems = 0, planes = 1;
+  bool sym = false;
+  int chunk = 0;
 };
 
 hipError_t batch_forces(BatchRun &R) {
@@ -1478,6 +1555,19 @@ hipError_t batch_forces(BatchRun &R) {
   L.out = R.planes > 1 ? R.d.part : R.d.acc;
   L.counter = R.d.counter + 1;
   L.kahan = R.kahan;
+  if (R.sym) {
+    L.islot = R.d.islot;
+    L.out = nullptr;
+    L.usum = R.d.usum;
+    L.chunk = R.chunk;
+    e = R.v->launch(L, R.s);
+    if (e == hipSuccess) {
+      e = steps::launch_batch_reduce_sym(R.d.usum, R.N, R.d.mid, R.d.moff,
+                                         R.d.mq, R.d.mubase, R.chunk, R.d.acc,
+                                         R.s);
+    }
+    return e;
+  }
   e = R.v->launch(L, R.s);
   if (e == hipSuccess && R.planes > 1) {
     e = steps::launch_batch_reduce(R.d.part, R.N, R.d.mid, R.d.kc, R.d.acc, R.s);
@@ -1566,7 +1656,17 @@ hipError_t upload_layout(BatchRun &R, const BatchLayout &L) {
     e = hipMemcpyAsync(R.d.kc, L.kc.data(), L.kc.size() * sizeof(int),
                        hipMemcpyHostToDevice, R.s);
   }
+  if (e == hipSuccess && L.sym) {
+    const std::vector<int> *src[3] = {&L.moff, &L.mq, &L.mubase};
+    int *dst[3] = {R.d.moff, R.d.mq, R.d.mubase};
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+      e = hipMemcpyAsync(dst[k], src[k]->data(), src[k]->size() * sizeof(int),
+                         hipMemcpyHostToDevice, R.s);
+    }
+  }
   R.planes = L.planes;
+  R.sym = L.sym;
+  R.chunk = L.chunk;
   // the host vectors must outlive the copies
   if (e == hipSuccess) e = hipStreamSynchronize(R.s);
   return e;
@@ -1764,11 +1864,14 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
                                    nullptr, nullptr, N, c->stream);
   if (e != hipSuccess) return hip_fail(e, "radix sort size query");
   const size_t max_tiles = (size_t)N / 128 + A + 1;
-  size_t max_items = 1, max_planes = 1;
+  size_t max_items = 1, max_planes = 1, max_usum = 0;
   for (const auto *v : cands) {  // every layout the run may use
-    const BatchLayout L = batch_layout(soff, v->r, v->tj);
+    const BatchLayout L = batch_layout(soff, v->r, v->tj, batch_is_sym(v));
     max_items = std::max(max_items, L.items.size());
     max_planes = std::max(max_planes, (size_t)L.planes);
+    if (L.sym) {
+      max_usum = std::max(max_usum, (size_t)L.nslots * 9 * (size_t)L.chunk);
+    }
   }
   const size_t n = (size_t)N, d8 = sizeof(double);
   Carve cv;
@@ -1790,6 +1893,9 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
                o_items = cv.take(max_items * sizeof(int4)),
                o_islot = cv.take(max_items * 4), o_kc = cv.take((size_t)A * 4),
                o_part = cv.take(max_planes > 1 ? max_planes * 3 * n * d8 : 0),
+               o_usum = cv.take(max_usum * d8),
+               o_moff = cv.take((size_t)A * 4), o_mq = cv.take((size_t)A * 4),
+               o_mub = cv.take((size_t)A * 4),
                o_cnt = cv.take(2 * 4);
   if ((rc = ensure(c, c->arena, cv.off, "ensemble"))) return rc;
   char *base = (char *)c->arena.p;
@@ -1825,6 +1931,10 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
   d.islot = (int *)(base + o_islot);
   d.kc = (int *)(base + o_kc);
   d.part = max_planes > 1 ? (double *)(base + o_part) : nullptr;
+  d.usum = max_usum ? (double *)(base + o_usum) : nullptr;
+  d.moff = (int *)(base + o_moff);
+  d.mq = (int *)(base + o_mq);
+  d.mubase = (int *)(base + o_mub);
   d.counter = (int *)(base + o_cnt);
 
   // the run uses its own stream (graph capture needs one), ordered after
@@ -1867,7 +1977,8 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
     const steps::BatchVariant *win = nullptr;
     for (const auto *v : cands) {
       R.v = v;
-      BATCH_TRY(upload_layout(R, batch_layout(soff, v->r, v->tj)), "layout");
+      BATCH_TRY(upload_layout(R, batch_layout(soff, v->r, v->tj, batch_is_sym(v))),
+                "layout");
       BATCH_TRY(steps::launch_batch_init(d.counter, s), "init");
       BATCH_TRY(hipEventRecord(t0, s), "hipEventRecord");
       BATCH_TRY(batch_forces(R), "ensemble force");
@@ -1884,10 +1995,11 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
     (void)hipEventDestroy(t1);
     R.v = win;
   }
-  BATCH_TRY(upload_layout(R, batch_layout(soff, R.v->r, R.v->tj)), "layout");
+  BATCH_TRY(upload_layout(R, batch_layout(soff, R.v->r, R.v->tj, batch_is_sym(R.v))),
+            "layout");
   BATCH_TRY(steps::launch_batch_init(d.counter, s), "init");
   BATCH_TRY(batch_forces(R), "ensemble force");
-  c->batch_tile = steps_tile{R.v->r, R.v->tj, 1, R.v->variant};
+  c->batch_tile = steps_tile{R.v->r, R.v->tj, R.planes, R.v->variant};
 
   // steps
   const bool use_graph = (b->flags & STEPS_BATCH_GRAPH) != 0;

@@ -763,6 +763,295 @@ __device__ __forceinline__ void sym_block_f64(
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric FP64 evaluation, j-quad layout (variant 30).  Same units, plane
+// and accumulator layout, reduction and near-block path as sym_block_f64;
+// the far blocks assign the matrix-core lanes the other way round.  In
+// v_mfma_f64_4x4x4_4b the four blocks now hold four different j-quads
+// against the same four i (an i-quad), and a wave sweeps its 16 i-quads for
+// each group of 16 j:
+//   * Gram product: r^2 (i row ii, j column jj of block b) = q_j +
+//     (-2 u_i, q_i) . (u_j, 1), lane jj + 4b + 16 ii;
+//   * j-side: the weights are already the A operand of a product that
+//     contracts over the i of the quad (lane bits 4-5), so one MFMA per
+//     i-quad, chained over the 16 i-quads, gives the j sums of all 64 i of
+//     the wave: no cross-lane reduction per group;
+//   * i-side: the weights transposed within each 4 x 4 block (lane permute)
+//     are the A operand of the product with the j operand -1.5 m_j (u_j, 1);
+//     each i-quad keeps its own accumulator, whose four blocks (one per
+//     j-quad) are added once per pass over the unit's j chunk.
+// Positions are taken relative to the centre cb of the i-block's box (not
+// of the tile's), so the i operands stay in registers for the whole pass;
+// the separation test bounds |u_i| + |u_j| by |c_w - cb| + e_w +
+// |c_t - cb| + e_t, and the Gram error stays below ~2 kSepSym^2 eps as
+// before.  The i-side rank-one term -u_i D_3 is linear in the sums and is
+// applied once at the end of the pass.
+// ---------------------------------------------------------------------------
+template <int TJ>
+__device__ __forceinline__ void sym_block_f64_q(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ soft, int stride, int i0, int iend, int jbeg,
+    int jend, const double *__restrict__ tinfo,
+    const double *__restrict__ iinfo, double *__restrict__ out,
+    double *__restrict__ jacc, int chunk, bool first, double2 *tile,
+    double *gT, double *qT, double *bT, double *jbuf) {
+  static_assert(TJ == kBlock, "one thread per tile particle in the j-side sum");
+  constexpr int NQ = 16;  // i-quads of a wave
+  const int tid = threadIdx.x;
+  const int l = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wbase = i0 + wv * 64;
+  const int last = iend - 1;
+  const int nw = max(0, min(64, iend - wbase));  // valid i of this wave
+  const double *X = pos, *Y = pos + stride, *Z = pos + 2 * (size_t)stride;
+  double *jb = jbuf + (size_t)wv * TJ * 3;  // this wave's [TJ][3] j sums
+
+  const bool valid = wbase + l < iend;
+  const int ip = min(wbase + l, last);
+  const double xi = X[ip], yi = Y[ip], zi = Z[ip], hi = soft[ip];
+  const int kk = l >> 4, cc = l & 3;
+  const double *Pc = cc == 0 ? X : (cc == 1 ? Y : Z);
+  double wb[7];
+  {
+    const double xs[1] = {xi}, ys[1] = {yi}, zs[1] = {zi}, hs[1] = {hi};
+    const bool vs[1] = {valid};
+    wave_box<1, double>(xs, ys, zs, hs, vs, wb);
+  }
+  // centre of the i-block's box (uniform over the workgroup)
+  const double cb[3] = {0.5 * (iinfo[0] + iinfo[3]), 0.5 * (iinfo[1] + iinfo[4]),
+                        0.5 * (iinfo[2] + iinfo[5])};
+  const double ccb = cc == 0 ? cb[0] : (cc == 1 ? cb[1] : cb[2]);
+  // |u_i| bound of this wave: |c_w - cb| + e_w
+  const double aw =
+      sqrt((0.5 * (wb[0] + wb[3]) - cb[0]) * (0.5 * (wb[0] + wb[3]) - cb[0]) +
+           (0.5 * (wb[1] + wb[4]) - cb[1]) * (0.5 * (wb[1] + wb[4]) - cb[1]) +
+           (0.5 * (wb[2] + wb[5]) - cb[2]) * (0.5 * (wb[2] + wb[5]) - cb[2])) +
+      0.5 * sqrt((wb[3] - wb[0]) * (wb[3] - wb[0]) +
+                 (wb[4] - wb[1]) * (wb[4] - wb[1]) +
+                 (wb[5] - wb[2]) * (wb[5] - wb[2]));
+
+  // i operands of the 16 i-quads, fixed for the pass: ag = (-2 u_i, q_i) at
+  // lane ii + 4b + 16k (i = 4q + ii), bi = -1.5 m_i (u_i, 1) at lane
+  // c + 4b + 16ii (i = 4q + ii; zero mass past iend)
+  double ag[NQ], bi[NQ], acci[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int ia = min(wbase + 4 * q + cc, last);
+    const double ux = X[ia] - cb[0], uy = Y[ia] - cb[1], uz = Z[ia] - cb[2];
+    ag[q] = kk == 0 ? -2.0 * ux
+                    : (kk == 1 ? -2.0 * uy
+                               : (kk == 2 ? -2.0 * uz : fma(uz, uz, fma(uy, uy, ux * ux))));
+    const int ib = wbase + 4 * q + kk;
+    const int ibc = min(ib, last);
+    const double m = ib < iend ? mass[ibc] : 0.0;
+    bi[q] = -1.5 * m * (cc < 3 ? Pc[ibc] - ccb : 1.0);
+    acci[q] = 0.0;
+  }
+  // near-block i-side sums (output layout: component cc of particle
+  // 16 r + 4 ((l >> 2) & 3) + (l >> 4)), compensated
+  double sum[4], cmp[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) sum[r] = cmp[r] = 0.0;
+  // transpose within 4 x 4 blocks: lane n + 4b + 16m reads n' = m, m' = n
+  const int tsrc = ((l >> 4) & 3) | (l & 12) | ((l & 3) << 4);
+  // this lane's j-side slot in a group of 16 j: j = 16 G + 4 b + jj, b the
+  // block, jj = l >> 4, component cc
+  const int jslot = (l & 12) + kk;
+
+  for (int jt = jbeg; jt < jend; jt += TJ) {
+    const double *ti = tinfo + (size_t)((jt - jbeg) / TJ) * 8;
+    __syncthreads();
+    {
+      const int k = tid;
+      const int j = min(jt + k, jend - 1);
+      const double mj = (jt + k < jend) ? mass[j] : 0.0;
+      const double xj = X[j], yj = Y[j], zj = Z[j];
+      tile[3 * k] = double2{xj, yj};
+      tile[3 * k + 1] = double2{zj, mj};
+      tile[3 * k + 2] = double2{soft[j], 0.0};
+      const double ux = xj - cb[0], uy = yj - cb[1], uz = zj - cb[2];
+      const int G = k >> 4, jl = k & 15;
+      gT[64 * G + jl] = ux;
+      gT[64 * G + 16 + jl] = uy;
+      gT[64 * G + 32 + jl] = uz;
+      gT[64 * G + 48 + jl] = 1.0;
+      qT[k] = fma(uz, uz, fma(uy, uy, ux * ux));
+      const double mm = -1.5 * mj;
+      const int bo = 64 * G + 16 * (jl & 3) + 4 * (jl >> 2);
+      bT[bo] = mm * ux;
+      bT[bo + 1] = mm * uy;
+      bT[bo + 2] = mm * uz;
+      bT[bo + 3] = mm;
+    }
+    const bool jown = jt + tid < jend;
+    const size_t jl = (size_t)(jt + tid - jbeg);
+    __syncthreads();
+
+    const double gxv = fmax(0.0, fmax(ti[0] - wb[3], wb[0] - ti[3]));
+    const double gyv = fmax(0.0, fmax(ti[1] - wb[4], wb[1] - ti[4]));
+    const double gzv = fmax(0.0, fmax(ti[2] - wb[5], wb[2] - ti[5]));
+    const double d2 = gxv * gxv + gyv * gyv + gzv * gzv;
+    const double hs = ti[6] + wb[6];
+    const bool far = d2 > fmax(hs * hs * (1.0 + 1e-6), 1e-30);
+    const double bt =
+        sqrt((0.5 * (ti[0] + ti[3]) - cb[0]) * (0.5 * (ti[0] + ti[3]) - cb[0]) +
+             (0.5 * (ti[1] + ti[4]) - cb[1]) * (0.5 * (ti[1] + ti[4]) - cb[1]) +
+             (0.5 * (ti[2] + ti[5]) - cb[2]) * (0.5 * (ti[2] + ti[5]) - cb[2])) +
+        0.5 * sqrt((ti[3] - ti[0]) * (ti[3] - ti[0]) +
+                   (ti[4] - ti[1]) * (ti[4] - ti[1]) +
+                   (ti[5] - ti[2]) * (ti[5] - ti[2]));
+    const bool sep = far && (aw + bt) <= kSepSym * sqrt(d2);
+    const bool use_mfma = __builtin_amdgcn_readfirstlane((int)sep) != 0;
+
+    if (nw == 0) {
+      // a wave past the end of the chunk: nothing on either side
+      for (int k = l; k < 3 * TJ; k += 64) jb[k] = 0.0;
+    } else if (use_mfma) {
+#pragma unroll 1
+      for (int G = 0; G < TJ / 16; ++G) {
+        const double bg = gT[64 * G + l];
+        const double cj = qT[16 * G + (l & 15)];
+        const double bj = bT[64 * G + l];
+        double aj = 0.0;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const double rr = mfma4(ag[q], bg, cj);
+          const double y = __builtin_amdgcn_rsq(rr);
+          const double y2 = y * y;
+          const double t = fma(rr, y2, -5.0 / 3.0);
+          const double w = (y * y2) * t;  // -(2/3) r^-3 (1 + 3/2 e)
+          aj = mfma4(w, bi[q], aj);
+          acci[q] = mfma4(__shfl(w, tsrc), bj, acci[q]);
+        }
+        // j-side of the group: D_c - u_{j,c} D_3 (D_3 from the quad's lane 3)
+        const double uj = gT[64 * G + 16 * cc + (l & 12) + kk];
+        const double f = fma(-uj, quad_bcast3(aj), aj);
+        if (cc < 3) jb[3 * (16 * G + jslot) + cc] = f;
+      }
+    } else {
+      // near block: the direct loops of sym_block_f64 (lane = i, then
+      // lane = j), results in the output layout
+      double tx = 0.0, ty = 0.0, tz = 0.0;
+      if (__builtin_amdgcn_readfirstlane((int)far)) {
+#pragma unroll 4
+        for (int k = 0; k < TJ; ++k) {
+          const double2 a = tile[3 * k], b = tile[3 * k + 1];
+          const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          const double w = newton_w64<true>(r2, b.y);
+          tx = fma(w, dx, tx);
+          ty = fma(w, dy, ty);
+          tz = fma(w, dz, tz);
+        }
+      } else {
+#pragma unroll 2
+        for (int k = 0; k < TJ; ++k) {
+          const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
+          const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
+          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+          const double h = c.x + hi;
+          double w = newton_w64<true>(r2, b.y);
+          if (r2 <= h * h) w = soft_w64(r2, h, b.y);
+          tx = fma(w, dx, tx);
+          ty = fma(w, dy, ty);
+          tz = fma(w, dz, tz);
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int src = 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
+        const double vx = __shfl(tx, src), vy = __shfl(ty, src), vz = __shfl(tz, src);
+        two_sum_add(sum[r], cmp[r],
+                    cc == 0 ? vx : (cc == 1 ? vy : (cc == 2 ? vz : 0.0)));
+      }
+      const bool farw = __builtin_amdgcn_readfirstlane((int)far) != 0;
+      for (int p = 0; p < TJ / 64; ++p) {
+        const int k = 64 * p + l;
+        const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        const double mown = valid ? mass[ip] : 0.0;
+        for (int q0 = 0; q0 < nw; q0 += 4) {
+          double qx[4], qy[4], qz[4], qm[4], qh[4];
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int ql = min(q0 + t, 63);
+            qx[t] = rl(xi, ql);
+            qy[t] = rl(yi, ql);
+            qz[t] = rl(zi, ql);
+            qm[t] = rl(mown, ql);
+            qh[t] = rl(hi, ql);
+          }
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const double dx = qx[t] - a.x, dy = qy[t] - a.y, dz = qz[t] - b.x;
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            double w = newton_w64<true>(r2, qm[t]);
+            if (!farw) {
+              const double h = c.x + qh[t];
+              if (r2 <= h * h) w = soft_w64(r2, h, qm[t]);
+            }
+            fx = fma(w, dx, fx);
+            fy = fma(w, dy, fy);
+            fz = fma(w, dz, fz);
+          }
+        }
+        jb[3 * k] = fx;
+        jb[3 * k + 1] = fy;
+        jb[3 * k + 2] = fz;
+      }
+    }
+    // this thread's accumulator entry (j = jt + tid), read while the other
+    // waves finish
+    double acc6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (!first && jown) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) acc6[c] = jacc[(size_t)c * chunk + jl];
+    }
+    __syncthreads();
+
+    // tile's j-side: the four waves' sums in order, into the accumulator
+    if (jown) {
+      const int k = tid;
+      double f[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        f[c] = ((jbuf[3 * k + c] + jbuf[3 * (TJ + k) + c]) +
+                jbuf[3 * (2 * TJ + k) + c]) + jbuf[3 * (3 * TJ + k) + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if (first) {
+          acc6[c] = f[c];
+          acc6[3 + c] = 0.0;
+        } else {
+          two_sum_add(acc6[c], acc6[3 + c], f[c]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) jacc[(size_t)c * chunk + jl] = acc6[c];
+    }
+  }
+
+  // far i-side: add each quad's four j-quad blocks (row rotations), keep
+  // quad q = 4r + b in the lanes of block b, then S = D_c - u_{i,c} D_3
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double v = acci[q];
+    v += row_ror<4>(v);
+    v += row_ror<8>(v);
+    if (((l >> 2) & 3) == (q & 3)) part[q >> 2] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int id = wbase + 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
+    const double ui = cc < 3 ? Pc[min(id, last)] - ccb : 0.0;
+    const double f = fma(-ui, quad_bcast3(part[r]), part[r]);
+    two_sum_add(sum[r], cmp[r], cc < 3 ? f : 0.0);
+    if (cc < 3 && id < iend) out[(size_t)cc * stride + id] = sum[r] + cmp[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // One block's share, mixed precision: pair arithmetic in FP32 on an FP32
 // shadow [5][stride] (x, y, z, m, h); v_rsq_f32 (~2^-23) used as is.  Each
 // tile's FP32 partial is added into an FP64 accumulator, or into a
@@ -774,7 +1063,7 @@ template <int R, int TJ, bool KAHAN, bool CULL>
 __device__ __forceinline__ void force_block_mixed(
     const float *__restrict__ shadow, int stride, int i0, int iend, int jbeg,
     int jend, const double *__restrict__ tinfo, double *__restrict__ out,
-    float4 *tpos, float *tsoft) {
+    int ostride, int obase, float4 *tpos, float *tsoft) {
   const int tid = threadIdx.x;
   const int ibase = i0 + (tid >> 6) * (64 * R) + (tid & 63);
   const float *X = shadow, *Y = shadow + stride, *Z = shadow + 2 * (size_t)stride;
@@ -883,14 +1172,15 @@ __device__ __forceinline__ void force_block_mixed(
   for (int r = 0; r < R; ++r) {
     const int i = ibase + 64 * r;
     if (i < iend) {
+      double *o = out + (i - obase);
       if (KAHAN) {
-        out[i] = (double)sx[r] - (double)cx[r];
-        out[(size_t)stride + i] = (double)sy[r] - (double)cy[r];
-        out[2 * (size_t)stride + i] = (double)sz[r] - (double)cz[r];
+        o[0] = (double)sx[r] - (double)cx[r];
+        o[(size_t)ostride] = (double)sy[r] - (double)cy[r];
+        o[2 * (size_t)ostride] = (double)sz[r] - (double)cz[r];
       } else {
-        out[i] = ax[r];
-        out[(size_t)stride + i] = ay[r];
-        out[2 * (size_t)stride + i] = az[r];
+        o[0] = ax[r];
+        o[(size_t)ostride] = ay[r];
+        o[2 * (size_t)ostride] = az[r];
       }
     }
   }
@@ -972,6 +1262,51 @@ __global__ __launch_bounds__(kBlock, 3) void k_force_f64_sym(
   }
 }
 
+// Symmetric FP64 kernel, j-quad layout of the far blocks (variant 30):
+// units, planes and accumulators as k_force_f64_sym.  Its far loop holds
+// the i operands of 16 i-quads and their accumulators in registers, so the
+// kernel runs two workgroups per CU.
+template <int TJ>
+__global__ __launch_bounds__(kBlock, 2) void k_force_f64_symq(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ soft, int n, int chunk, int nchunks,
+    const double *__restrict__ tinfo, double *__restrict__ iplane,
+    double *__restrict__ jacc) {
+  __shared__ double2 tile[3 * TJ];
+  __shared__ double gram[4 * TJ];
+  __shared__ double bmat[4 * TJ];
+  __shared__ double qj[TJ];
+  __shared__ double jbuf[4 * TJ * 3];
+  const int nsym = nchunks * (nchunks - 1) / 2;
+  const int u = blockIdx.x;
+  int R, s;
+  if (u < nsym) {
+    s = (int)((1.0 + sqrt(1.0 + 8.0 * (double)u)) * 0.5);
+    while (s * (s - 1) / 2 > u) --s;
+    while ((s + 1) * s / 2 <= u) ++s;
+    R = u - s * (s - 1) / 2;
+  } else {
+    R = s = u - nsym;
+  }
+  const int ibeg = R * chunk, iend = min(n, ibeg + chunk);
+  const int jbeg = s * chunk, jend = min(n, jbeg + chunk);
+  double *out = iplane + (size_t)s * 3 * (size_t)n;
+  const double *ti = tinfo + (size_t)(jbeg / TJ) * 8;
+  if (R == s) {
+    for (int i0 = ibeg; i0 < iend; i0 += kBlock) {
+      force_block_f64_mfma<TJ>(pos, mass, soft, n, i0, iend, jbeg, jend, ti,
+                               out, tile, gram, bmat);
+    }
+    return;
+  }
+  double *ja = jacc + (size_t)u * 6 * (size_t)chunk;
+  for (int i0 = ibeg; i0 < iend; i0 += kBlock) {
+    sym_block_f64_q<TJ>(pos, mass, soft, n, i0, iend, jbeg, jend, ti,
+                        tinfo + (size_t)(i0 / TJ) * 8, out, ja, chunk,
+                        i0 == ibeg, tile, gram, qj, bmat, jbuf);
+  }
+}
+
 // acc[d][perm[p]] for p in chunk k: planes k .. Q-1 of iplane, then the
 // (value, error) accumulators of units (R, k), R < k, in that order,
 // compensated
@@ -1007,7 +1342,7 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(
   force_block_mixed<R, TJ, KAHAN, CULL>(
       shadow, n, blockIdx.x * (kBlock * R), n, jbeg, min(n, jbeg + jchunk),
       CULL ? tinfo + (size_t)(jbeg / TJ) * 8 : nullptr,
-      out + (size_t)blockIdx.y * 3 * (size_t)n, tpos, tsoft);
+      out + (size_t)blockIdx.y * 3 * (size_t)n, n, 0, tpos, tsoft);
 }
 
 // ---------------------------------------------------------------------------
@@ -1037,12 +1372,12 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed(
 // memory clobber is a compiler-only barrier (it emits no instruction).
 __device__ __forceinline__ void lds_step_fence() { asm volatile("" ::: "memory"); }
 
-template <int R, bool KAHAN>
+template <int R, bool KAHAN, bool REFINE = false>
 __device__ __forceinline__ void sym_block_mixed(
     const float *__restrict__ shadow, int stride, int i0, int iend, int jbeg,
     int jend, const double *__restrict__ tinfo, double *__restrict__ out,
-    double *__restrict__ jacc, int chunk, bool first, float4 *tpos,
-    float *tsoft, float *jl) {
+    int ostride, int obase, double *__restrict__ jacc, int chunk, bool first,
+    float4 *tpos, float *tsoft, float *jl) {
   constexpr int TJ = 256;
   static_assert(TJ == kBlock, "one thread per tile particle");
   const int tid = threadIdx.x;
@@ -1108,7 +1443,14 @@ __device__ __forceinline__ void sym_block_mixed(
               const float dx = p.x - xi[r], dy = p.y - yi[r], dz = p.z - zi[r];
               const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
               const float y = __builtin_amdgcn_rsqf(r2);
-              const float y3 = (y * y) * y;
+              const float y2 = y * y;
+              float y3 = y2 * y;
+              if (REFINE) {
+                // one Newton step on r^-3: with e = 1 - r^2 y^2,
+                // r^-3 = y^3 (1 + 3/2 e) + O(e^2)
+                const float e = fmaf(-r2, y2, 1.0f);
+                y3 = fmaf(1.5f * e, y3, y3);
+              }
               const float wi = p.w * y3, wj = mi[r] * y3;
               tx[r] = fmaf(wi, dx, tx[r]);
               ty[r] = fmaf(wi, dy, ty[r]);
@@ -1137,7 +1479,9 @@ __device__ __forceinline__ void sym_block_mixed(
               const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
               const float h = hj + hi[r];
               const float y = __builtin_amdgcn_rsqf(r2);
-              float w = (y * y) * y;
+              const float y2 = y * y;
+              float w = y2 * y;
+              if (REFINE) w = fmaf(1.5f * fmaf(-r2, y2, 1.0f), w, w);
               if (r2 <= h * h) w = soft_w32(r2, h, 1.0f);
               const float wi = p.w * w, wj = mi[r] * w;
               tx[r] = fmaf(wi, dx, tx[r]);
@@ -1221,14 +1565,15 @@ __device__ __forceinline__ void sym_block_mixed(
   for (int r = 0; r < R; ++r) {
     const int i = wbase + 64 * r + l;
     if (valid[r]) {
+      double *o = out + (i - obase);
       if (KAHAN) {
-        out[i] = (double)sx[r] - (double)cx[r];
-        out[(size_t)stride + i] = (double)sy[r] - (double)cy[r];
-        out[2 * (size_t)stride + i] = (double)sz[r] - (double)cz[r];
+        o[0] = (double)sx[r] - (double)cx[r];
+        o[(size_t)ostride] = (double)sy[r] - (double)cy[r];
+        o[2 * (size_t)ostride] = (double)sz[r] - (double)cz[r];
       } else {
-        out[i] = ax[r];
-        out[(size_t)stride + i] = ay[r];
-        out[2 * (size_t)stride + i] = az[r];
+        o[0] = ax[r];
+        o[(size_t)ostride] = ay[r];
+        o[2 * (size_t)ostride] = az[r];
       }
     }
   }
@@ -1236,7 +1581,7 @@ __device__ __forceinline__ void sym_block_mixed(
 
 // Symmetric mixed kernel: the unit grid of k_force_f64_sym; diagonal units
 // run the one-sided mixed block (same accumulation) into plane s.
-template <int R, bool KAHAN>
+template <int R, bool KAHAN, bool REFINE>
 __global__ __launch_bounds__(kBlock) void k_force_mixed_sym(
     const float *__restrict__ shadow, int n, int chunk, int nchunks,
     const double *__restrict__ tinfo, double *__restrict__ iplane,
@@ -1262,14 +1607,14 @@ __global__ __launch_bounds__(kBlock) void k_force_mixed_sym(
   if (cr == cs) {
     for (int i0 = ibeg; i0 < iend; i0 += kBlock * R) {
       force_block_mixed<R, 256, KAHAN, true>(shadow, n, i0, iend, jbeg, jend,
-                                             ti, out, tpos, tsoft);
+                                             ti, out, n, 0, tpos, tsoft);
     }
     return;
   }
   double *ja = jacc + (size_t)u * 6 * (size_t)chunk;
   for (int i0 = ibeg; i0 < iend; i0 += kBlock * R) {
-    sym_block_mixed<R, KAHAN>(shadow, n, i0, iend, jbeg, jend, ti, out, ja,
-                              chunk, i0 == ibeg, tpos, tsoft, jl);
+    sym_block_mixed<R, KAHAN, REFINE>(shadow, n, i0, iend, jbeg, jend, ti, out, n, 0,
+                              ja, chunk, i0 == ibeg, tpos, tsoft, jl);
   }
 }
 
@@ -1341,8 +1686,73 @@ __global__ __launch_bounds__(kBlock) void k_batch_force_mixed(
     double *o = islot ? out + (size_t)islot[it] * 3 * (size_t)stride : out;
     force_block_mixed<R, TJ, KAHAN, true>(shadow, stride, w.x, w.y, w.z, w.w,
                                           tinfo + (size_t)tbase[it] * 8, o,
-                                          tpos, tsoft);
+                                          stride, 0, tpos, tsoft);
   }
+}
+
+// Symmetric ensemble kernel, mixed precision: block u is unit u of the
+// layout, a chunk pair (R, s), R <= s, of one member: items[u] = (ibeg,
+// iend, jbeg, jend) in the sorted arena, tbase[u] the tile of jbeg, and
+// islot[u] its slot of usum, [9][chunk] doubles: the i-side sums of chunk
+// R's particles, then the (value, error) j-side accumulator of chunk s's.
+// A diagonal unit (ibeg == jbeg) sums its chunk one-sided into the i-side.
+// Units are of nearly equal cost, so the grid is one workgroup per unit.
+template <int R, bool KAHAN>
+__global__ __launch_bounds__(kBlock) void k_batch_force_mixed_sym(
+    const float *__restrict__ shadow, int stride, const int4 *__restrict__ units,
+    const int *__restrict__ tbase, const int *__restrict__ uslot, int nunits,
+    const double *__restrict__ tinfo, double *__restrict__ usum, int chunk) {
+  __shared__ float4 tpos[256];
+  __shared__ float tsoft[256];
+  __shared__ float jl[4 * 3 * 256];
+  const int u = blockIdx.x;
+  if (u >= nunits) return;
+  const int4 w = units[u];
+  const double *ti = tinfo + (size_t)tbase[u] * 8;
+  double *slot = usum + (size_t)uslot[u] * 9 * (size_t)chunk;
+  if (w.x == w.z) {
+    for (int i0 = w.x; i0 < w.y; i0 += kBlock * R) {
+      force_block_mixed<R, 256, KAHAN, true>(shadow, stride, i0, w.y, w.z, w.w,
+                                             ti, slot, chunk, w.x, tpos, tsoft);
+    }
+    return;
+  }
+  for (int i0 = w.x; i0 < w.y; i0 += kBlock * R) {
+    sym_block_mixed<R, KAHAN>(shadow, stride, i0, w.y, w.z, w.w, ti, slot,
+                              chunk, w.x, slot + 3 * (size_t)chunk, chunk,
+                              i0 == w.x, tpos, tsoft, jl);
+  }
+}
+
+// acc[d][p] for arena slot p of member a = mid[p], in chunk k of that
+// member: the i-side sums of units (k, t), t = k .. Q_a - 1, then the j-side
+// (value, error) accumulators of units (R, k), R < k, compensated, in that
+// order.  Unit (R, s) of member a sits in slot ubase[a] + s (s + 1) / 2 + R.
+__global__ __launch_bounds__(kBlock) void k_batch_reduce_sym(
+    const double *__restrict__ usum, int n, const int *__restrict__ mid,
+    const int *__restrict__ moff, const int *__restrict__ mq,
+    const int *__restrict__ mubase, int chunk, double *__restrict__ acc) {
+  const size_t total = 3 * (size_t)n;
+  const size_t q = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (q >= total) return;
+  const int d = (int)(q / n), p = (int)(q - (size_t)d * n);
+  const int a = mid[p];
+  const int loc0 = p - moff[a];
+  const int k = loc0 / chunk, loc = loc0 - k * chunk;
+  const int nq = mq[a];
+  const size_t ub = (size_t)mubase[a], S = 9 * (size_t)chunk;
+  double s = 0.0, c = 0.0;
+  for (int t = k; t < nq; ++t) {
+    two_sum_add(s, c, usum[(ub + (size_t)t * (t + 1) / 2 + k) * S +
+                           (size_t)d * chunk + loc]);
+  }
+  const size_t row = ub + (size_t)k * (k + 1) / 2;
+  for (int r = 0; r < k; ++r) {
+    const double *js = usum + (row + r) * S + 3 * (size_t)chunk;
+    two_sum_add(s, c, js[(size_t)d * chunk + loc]);
+    c += js[(size_t)(3 + d) * chunk + loc];
+  }
+  acc[q] = s + c;
 }
 
 // ---------------------------------------------------------------------------
@@ -1369,7 +1779,7 @@ hipError_t launch_f64_mfma(const ForceLaunch &L, hipStream_t s) {
 // Units of the symmetric kernel: Q chunks of jchunk particles (Q = jsplit)
 // must cover [0, n) with every chunk non-empty; checked here, before the
 // launch, since the kernel indexes iplane, jacc and tinfo by chunk.
-template <int TJ>
+template <int TJ, bool QUAD>
 hipError_t launch_f64_sym(const ForceLaunch &L, hipStream_t s) {
   const int q = L.jsplit;
   if (L.jchunk <= 0 || L.jchunk % TJ != 0 || q < 1 || q > 4096 ||
@@ -1378,15 +1788,21 @@ hipError_t launch_f64_sym(const ForceLaunch &L, hipStream_t s) {
     return hipErrorInvalidValue;
   }
   const int units = q * (q + 1) / 2;
-  hipLaunchKernelGGL((k_force_f64_sym<TJ>), dim3(units), dim3(kBlock), 0, s,
-                     L.pos, L.mass, L.soft, L.n, L.jchunk, q, L.tinfo, L.out,
-                     L.jacc);
+  if (QUAD) {
+    hipLaunchKernelGGL((k_force_f64_symq<TJ>), dim3(units), dim3(kBlock), 0, s,
+                       L.pos, L.mass, L.soft, L.n, L.jchunk, q, L.tinfo, L.out,
+                       L.jacc);
+  } else {
+    hipLaunchKernelGGL((k_force_f64_sym<TJ>), dim3(units), dim3(kBlock), 0, s,
+                       L.pos, L.mass, L.soft, L.n, L.jchunk, q, L.tinfo, L.out,
+                       L.jacc);
+  }
   return hipGetLastError();
 }
 
 // Symmetric mixed kernel: the chunk layout is checked as for the FP64
 // symmetric kernel.
-template <int R>
+template <int R, bool REFINE>
 hipError_t launch_mixed_sym(const ForceLaunch &L, hipStream_t s) {
   const int q = L.jsplit;
   if (!L.shadow || L.jchunk <= 0 || L.jchunk % 256 != 0 || q < 1 ||
@@ -1396,10 +1812,10 @@ hipError_t launch_mixed_sym(const ForceLaunch &L, hipStream_t s) {
   }
   const int units = q * (q + 1) / 2;
   if (L.kahan) {
-    hipLaunchKernelGGL((k_force_mixed_sym<R, true>), dim3(units), dim3(kBlock),
+    hipLaunchKernelGGL((k_force_mixed_sym<R, true, REFINE>), dim3(units), dim3(kBlock),
                        0, s, L.shadow, L.n, L.jchunk, q, L.tinfo, L.out, L.jacc);
   } else {
-    hipLaunchKernelGGL((k_force_mixed_sym<R, false>), dim3(units),
+    hipLaunchKernelGGL((k_force_mixed_sym<R, false, REFINE>), dim3(units),
                        dim3(kBlock), 0, s, L.shadow, L.n, L.jchunk, q, L.tinfo,
                        L.out, L.jacc);
   }
@@ -1453,6 +1869,24 @@ hipError_t launch_batch_f64_mfma(const BatchLaunch &L, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int R>
+hipError_t launch_batch_mixed_sym(const BatchLaunch &L, hipStream_t s) {
+  if (!L.usum || L.chunk <= 0 || L.chunk % 256 != 0 || L.nitems < 0) {
+    return hipErrorInvalidValue;
+  }
+  if (L.nitems == 0) return hipSuccess;
+  if (L.kahan) {
+    hipLaunchKernelGGL((k_batch_force_mixed_sym<R, true>), dim3(L.nitems),
+                       dim3(kBlock), 0, s, L.shadow, L.stride, L.items, L.tbase,
+                       L.islot, L.nitems, L.tinfo, L.usum, L.chunk);
+  } else {
+    hipLaunchKernelGGL((k_batch_force_mixed_sym<R, false>), dim3(L.nitems),
+                       dim3(kBlock), 0, s, L.shadow, L.stride, L.items, L.tbase,
+                       L.islot, L.nitems, L.tinfo, L.usum, L.chunk);
+  }
+  return hipGetLastError();
+}
+
 template <int R, int TJ>
 hipError_t launch_batch_mixed(const BatchLaunch &L, hipStream_t s) {
   if (L.kahan) {
@@ -1473,7 +1907,8 @@ hipError_t launch_batch_mixed(const BatchLaunch &L, hipStream_t s) {
 // (wave, tile) culling of the softening test; 4 = matrix-core far field
 // (with 2: sorted input; a wave owns 64 particles, so it is listed as r = 1);
 // 8 = symmetric units (FP64: with 2 and 4; mixed: with 2; jsplit is the
-// chunk count).
+// chunk count); 16 = FP64 symmetric: the j-quad layout of the far blocks;
+// mixed symmetric: one Newton step on the FP32 r^-3.
 #define F64_SET(R)                                                  \
   {kClassF64, R, 128, 0, launch_f64<R, 128, true, false>},          \
       {kClassF64, R, 128, 1, launch_f64<R, 128, false, false>},     \
@@ -1487,10 +1922,13 @@ const ForceVariant kVariants[] = {
     F64_SET(1),         F64_SET(2),         F64_SET(4),         F64_SET(8),
     {kClassF64, 1, 128, 6, launch_f64_mfma<128>},
     {kClassF64, 1, 256, 6, launch_f64_mfma<256>},
-    {kClassF64, 1, 256, 14, launch_f64_sym<256>},
+    {kClassF64, 1, 256, 14, launch_f64_sym<256, false>},
+    {kClassF64, 1, 256, 30, launch_f64_sym<256, true>},
     MIXED_SET(1, 128),  MIXED_SET(2, 256),  MIXED_SET(4, 256),  MIXED_SET(8, 256),
-    {kClassMixed, 2, 256, 10, launch_mixed_sym<2>},
-    {kClassMixed, 4, 256, 10, launch_mixed_sym<4>},
+    {kClassMixed, 2, 256, 10, launch_mixed_sym<2, false>},
+    {kClassMixed, 4, 256, 10, launch_mixed_sym<4, false>},
+    {kClassMixed, 2, 256, 26, launch_mixed_sym<2, true>},
+    {kClassMixed, 4, 256, 26, launch_mixed_sym<4, true>},
 };
 
 // ensemble variants: always culled (the ensemble keeps its state sorted)
@@ -1503,6 +1941,8 @@ const BatchVariant kBatchVariants[] = {
     {kClassMixed, 1, 128, 2, launch_batch_mixed<1, 128>},
     {kClassMixed, 2, 256, 2, launch_batch_mixed<2, 256>},
     {kClassMixed, 4, 256, 2, launch_batch_mixed<4, 256>},
+    {kClassMixed, 2, 256, 10, launch_batch_mixed_sym<2>},
+    {kClassMixed, 4, 256, 10, launch_batch_mixed_sym<4>},
 };
 
 }  // namespace
@@ -1531,6 +1971,18 @@ hipError_t launch_reduce_sym(const double *iplane, const double *jacc, int n,
   }
   hipLaunchKernelGGL(k_reduce_sym, dim3(ceil_div(3LL * n, kBlock)),
                      dim3(kBlock), 0, s, iplane, jacc, n, chunk, nchunks, perm,
+                     acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce_sym(const double *usum, int n, const int *mid,
+                                   const int *moff, const int *mq,
+                                   const int *mubase, int chunk, double *acc,
+                                   hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (chunk <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_batch_reduce_sym, dim3(ceil_div(3LL * n, kBlock)),
+                     dim3(kBlock), 0, s, usum, n, mid, moff, mq, mubase, chunk,
                      acc);
   return hipGetLastError();
 }

@@ -33,6 +33,8 @@ constexpr int kVarNoE2 = 1;  // FP64: r^-3 correction to first order only
 constexpr int kVarCull = 2;  // sorted input, (wave, tile) softening culling
 constexpr int kVarMfma = 4;  // FP64 far field on the matrix cores (with kVarCull)
 constexpr int kVarSym = 8;   // each pair once, both sides kept (with kVarMfma)
+constexpr int kVarQuad = 16; // symmetric FP64: j-quad layout of the far blocks;
+                             // symmetric mixed: Newton step on the FP32 r^-3
 
 struct ForceVariant {
   int cls;   // PrecClass
@@ -55,6 +57,11 @@ struct BatchLaunch {
   double *out = nullptr;          // [planes][3][stride]
   int *counter = nullptr;         // work counter, 0 before the launch
   int kahan = 0;
+  // symmetric variants: items are chunk-pair units, islot their slots of
+  // usum ([slots][9][chunk]: i-side [3][chunk], j-side (value, error)
+  // [6][chunk])
+  double *usum = nullptr;
+  int chunk = 0;
 };
 
 struct BatchVariant {
@@ -81,6 +88,13 @@ hipError_t launch_batch_kick_end(const double *pos, double *vel,
 hipError_t launch_batch_reduce(const double *part, int n, const int *mid,
                                const int *kc, double *acc, hipStream_t s);
 hipError_t launch_batch_advance(int *counter, hipStream_t s);
+// symmetric ensemble: acc [3][n] (sorted arena) from the unit slots of
+// usum; member a starts at slot moff[a] of the arena, has mq[a] chunks and
+// its unit (R, s) in slot mubase[a] + s (s + 1) / 2 + R
+hipError_t launch_batch_reduce_sym(const double *usum, int n, const int *mid,
+                                   const int *moff, const int *mq,
+                                   const int *mubase, int chunk, double *acc,
+                                   hipStream_t s);
 hipError_t launch_batch_tile_info_f64(const double *soa, int stride,
                                       const int *beg, const int *end,
                                       int ntiles, double *info, hipStream_t s);

@@ -187,6 +187,43 @@ def test_batch_fp64_kernel_matches_oracle(st, shape):
         assert err.max() <= 1e-12, (shape, b, err.max())
 
 
+# every mixed ensemble kernel, one-sided (variant 2) and symmetric (variant
+# 10), forced in turn, in both accumulations
+@pytest.mark.parametrize("shape", [(1, 128, 2), (2, 256, 2), (4, 256, 2),
+                                   (2, 256, 10), (4, 256, 10)])
+@pytest.mark.parametrize("prec", ["mixed", "kahan"])
+def test_batch_mixed_kernel_matches_oracle(st, prec, shape):
+    members = _members()
+    ctx = st.Context(0, precision=prec)
+    ctx.set_tile(shape[0], shape[1], 1, shape[2])
+    acc, offs = _zero_step_forces(st, members, ctx)
+    tile = st.steps_batch_tile(ctx)
+    ctx.close()
+    assert (tile["r"], tile["tj"], tile["variant"]) == shape
+    for b, m in enumerate(members):
+        if m.n < 2:
+            continue
+        ref = oracle.forces(m.pos, m.mass, m.soft)
+        err = np.linalg.norm(acc[:, offs[b]:offs[b + 1]] - ref, axis=0) / \
+            np.linalg.norm(ref, axis=0)
+        assert np.median(err) <= 1e-5 and err.max() <= 1e-4, \
+            (prec, shape, b, np.median(err), err.max())
+
+
+def test_batch_symmetric_graph_bitwise_and_repeatable(st):
+    # the symmetric ensemble kernel: graph replay equals launches, bitwise,
+    # and two runs agree bitwise
+    members = _members()
+    out = []
+    for flags in (st.STEPS_BATCH_GRAPH, 0, st.STEPS_BATCH_GRAPH):
+        ctx = st.Context(0, precision="mixed")
+        ctx.set_tile(4, 256, 1, 10)
+        out.append(_run(st, members, flags, ctx=ctx))
+        ctx.close()
+    for x, y, z in zip(out[0][1:4], out[1][1:4], out[2][1:4]):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
 def test_batch_forced_tile_must_name_an_ensemble_kernel(st):
     members = _members()
     ctx = st.Context(0, precision="fp64")

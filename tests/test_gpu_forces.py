@@ -72,7 +72,7 @@ def _variants(st):
         ctx = st.Context(0, precision=prec)
         for r in (1, 2, 4, 8):
             for tj in (128, 256):
-                for var in (0, 1, 2, 3, 6, 10, 14):
+                for var in (0, 1, 2, 3, 6, 10, 14, 26, 30):
                     for js in (1, 3, 7):
                         try:
                             ctx.set_tile(r, tj, js, var)
@@ -88,11 +88,11 @@ def test_every_launch_shape(st):
     pos, mass, soft = clustered(1537, 23, 0.1)
     ref = oracle.forces(pos, mass, soft)
     shapes = _variants(st)
-    # FP64: 4 r x 4 variants + two matrix-core tiles + the symmetric one;
-    # mixed and Kahan: 4 r x 2 variants + the symmetric one at r = 2 and 4;
-    # 3 splits each (for the symmetric kernels 1, 3 and 7 chunks, the last
-    # one a single particle)
-    assert len(shapes) == (19 + 10 + 10) * 3
+    # FP64: 4 r x 4 variants + two matrix-core tiles + the two symmetric
+    # ones; mixed and Kahan: 4 r x 2 variants + the symmetric one, plain and
+    # with the Newton step, at r = 2 and 4; 3 splits each (for the symmetric
+    # kernels 1, 3 and 7 chunks, the last one a single particle)
+    assert len(shapes) == (20 + 12 + 12) * 3
     ctxs = {p: st.Context(0, precision=p) for p in ("fp64", "mixed", "kahan")}
     for prec, r, tj, var, js in shapes:
         ctx = ctxs[prec]
@@ -143,7 +143,7 @@ def test_autotune_full_size_includes_symmetric(st, prec, tmp_path):
     p, m, h = dev(ps.pos), dev(ps.mass), dev(ps.soft)
     tile = st.steps_autotune(p, m, h, ctx, cache=str(tmp_path / "t.json"))
     print("tuned at 2^18 (%s):" % prec, tile, flush=True)
-    assert tile["variant"] in ((0, 3, 6, 14) if prec == "fp64" else (0, 2, 10))
+    assert tile["variant"] in ((0, 3, 6, 14, 30) if prec == "fp64" else (0, 2, 10))
     got = host(st.steps_forces(p, m, h, ctx=ctx))
     ctx.close()
     idx = np.random.default_rng(11).choice(ps.n, 128, replace=False)
@@ -176,26 +176,28 @@ def test_matrix_core_kernel_parity(st, n, tj):
 
 @pytest.mark.parametrize("q", [2, 3, 8, 0])
 @pytest.mark.parametrize("kind", ["stereo", "clustered"])
-def test_symmetric_kernel_parity(st, kind, q):
-    # variant 14: each pair between two chunks evaluated once and applied to
-    # both particles.  Ragged n; q chunks (0: the built-in count); the
-    # clustered set puts near and softened blocks between chunks (the direct
-    # loop of the j-side), the stereographic one mostly matrix-core blocks
+@pytest.mark.parametrize("var", [14, 30])
+def test_symmetric_kernel_parity(st, kind, q, var):
+    # variants 14 and 30 (two lane layouts of the far blocks): each pair
+    # between two chunks evaluated once and applied to both particles.
+    # Ragged n; q chunks (0: the built-in count); the clustered set puts near
+    # and softened blocks between chunks (the direct loop of the j-side), the
+    # stereographic one mostly matrix-core blocks
     if kind == "stereo":
         ps = synth.config(2, n=20001)
         pos, mass, soft = ps.pos, ps.mass, ps.soft
     else:
         pos, mass, soft = clustered(9000, 37, 0.1)
     ctx = st.Context(0, precision="fp64")
-    ctx.set_tile(1, 256, q, 14)
+    ctx.set_tile(1, 256, q, var)
     got = _gpu_forces(st, pos, mass, soft, ctx)
     again = _gpu_forces(st, pos, mass, soft, ctx)
     tile = ctx.get_tile(mass.size)
     ctx.close()
     assert np.array_equal(got, again)
-    assert tile["variant"] == 14 and tile["jsplit"] >= 1
+    assert tile["variant"] == var and tile["jsplit"] >= 1
     err = rel_err(got, oracle.forces(pos, mass, soft))
-    _report("fp64 symmetric %s q=%d (jsplit %d)" % (kind, q, tile["jsplit"]), err)
+    _report("fp64 symmetric v%d %s q=%d (jsplit %d)" % (var, kind, q, tile["jsplit"]), err)
     assert np.all(np.isfinite(got))
     assert err.max() <= FP64_TOL
 
@@ -203,26 +205,29 @@ def test_symmetric_kernel_parity(st, kind, q):
 @pytest.mark.parametrize("r,q", [(2, 2), (4, 3), (2, 8), (4, 0)])
 @pytest.mark.parametrize("kind", ["stereo", "clustered"])
 @pytest.mark.parametrize("prec", ["mixed", "kahan"])
-def test_symmetric_mixed_kernel_parity(st, prec, kind, r, q):
-    # variant 10: FP32 pairs, one weight per pair for both particles, FP64 or
-    # Kahan FP32 accumulation; ragged n, q chunks (0: the built-in count), r
-    # particles per lane; the clustered set has softened and coincident pairs
-    # between chunks.  Mixed bar, and bitwise repeats
+@pytest.mark.parametrize("var", [10, 26])
+def test_symmetric_mixed_kernel_parity(st, prec, kind, r, q, var):
+    # variants 10 and 26 (the latter with a Newton step on r^-3): FP32 pairs,
+    # one weight per pair for both particles, FP64 or Kahan FP32
+    # accumulation; ragged n, q chunks (0: the built-in count), r particles
+    # per lane; the clustered set has softened and coincident pairs between
+    # chunks.  Mixed bar, and bitwise repeats
     if kind == "stereo":
         ps = synth.config(2, n=20001)
         pos, mass, soft = ps.pos, ps.mass, ps.soft
     else:
         pos, mass, soft = clustered(9000, 37, 0.1)
     ctx = st.Context(0, precision=prec)
-    ctx.set_tile(r, 256, q, 10)
+    ctx.set_tile(r, 256, q, var)
     got = _gpu_forces(st, pos, mass, soft, ctx)
     again = _gpu_forces(st, pos, mass, soft, ctx)
     tile = ctx.get_tile(mass.size)
     ctx.close()
     assert np.array_equal(got, again)
-    assert tile["variant"] == 10
+    assert tile["variant"] == var
     err = rel_err(got, oracle.forces(pos, mass, soft))
-    _report("%s symmetric %s r=%d q=%d (jsplit %d)" % (prec, kind, r, q, tile["jsplit"]), err)
+    _report("%s symmetric v%d %s r=%d q=%d (jsplit %d)"
+            % (prec, var, kind, r, q, tile["jsplit"]), err)
     assert np.all(np.isfinite(got))
     assert np.median(err) <= 1e-5
     assert err.max() <= 1e-3
@@ -252,7 +257,7 @@ def test_symmetric_kernel_ragged_default_shape(st):
     n = 262144 + 37
     ps = synth.config(2, n=n)
     ctx = st.Context(0, precision="fp64")
-    assert ctx.get_tile(n)["variant"] == 14
+    assert ctx.get_tile(n)["variant"] in (14, 30)
     got = _gpu_forces(st, ps.pos, ps.mass, ps.soft, ctx)
     ctx.close()
     rng = np.random.default_rng(6)
@@ -262,16 +267,17 @@ def test_symmetric_kernel_ragged_default_shape(st):
     assert err.max() <= FP64_TOL
 
 
-def test_symmetric_kernel_full_size_sampled(st):
+@pytest.mark.parametrize("var", [14, 30])
+def test_symmetric_kernel_full_size_sampled(st, var):
     # N = 2^18 with the built-in chunk count; oracle on 256 sampled rows
     ps = synth.config(2)
     ctx = st.Context(0, precision="fp64")
-    ctx.set_tile(1, 256, 0, 14)
+    ctx.set_tile(1, 256, 0, var)
     got = _gpu_forces(st, ps.pos, ps.mass, ps.soft, ctx)
     ctx.close()
     idx = np.random.default_rng(5).choice(ps.n, 256, replace=False)
     err = rel_err(got[:, idx], oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx))
-    _report("fp64 symmetric config2 sampled", err)
+    _report("fp64 symmetric v%d config2 sampled" % var, err)
     assert err.max() <= FP64_TOL
 
 
