@@ -335,7 +335,9 @@ int steps_run_adaptive_ctx(steps_ctx *ctx, double *pos, double *vel,
  * give bitwise identical results). */
 #define STEPS_BATCH_GRAPH 1u
 /* Before stepping, time each compiled ensemble kernel on the first force
- * evaluation and keep the fastest (steps_batch_tile reports it). */
+ * evaluation and keep the fastest (steps_batch_tile reports it).  The choice
+ * is kept in the context for its precision and list of member sizes: a
+ * later run with the same sizes uses it without timing again. */
 #define STEPS_BATCH_AUTOTUNE 2u
 
 typedef struct steps_batch {

@@ -34,6 +34,10 @@ constexpr int64_t kSymMinN = 262144;
 // no longer fill the device evenly and the one-sided kernel is used
 constexpr int kSymMinChunks = 64;
 constexpr int64_t kMixedSymR4MinN = 524288;
+// from here the FP64 symmetric kernel takes its j-quad layout (variant 30):
+// 108.8 against 112.3 ms at 2^19, 1559 against 1696 ms at 2^21, and 30.8
+// against 30.4 ms at 2^18
+constexpr int64_t kSymQuadMinN = 524288;
 
 thread_local std::string t_err;
 
@@ -83,6 +87,9 @@ struct steps_ctx {
   Buffer arena;    // spatial-sort scratch (keys, permutation, sorted copy)
   Buffer diag;     // energy diagnostic: potential and reduction partials
   steps_tile batch_tile = {0, 0, 0, 0};  // shape of the last ensemble run
+  // ensemble kernels chosen by STEPS_BATCH_AUTOTUNE: (kernel class, hash of
+  // the active members' sizes) -> index into steps::batch_variants
+  std::vector<std::pair<std::pair<int, uint64_t>, int>> batch_tuned;
   // periodic geometry (steps_ctx_set_periodic): images 0 = open sphere
   double box_L = 0.0;
   int images = STEPS_IMAGES_NONE;
@@ -226,9 +233,11 @@ int heuristic_jsplit(int cls, int64_t n, int r, int tj, int variant) {
 
 // Launch shape: a forced tile, else a shape tuned for (class, n), else the
 // heuristic, measured on MI355X at N = 2^15 ... 2^21:
-//   * FP64 from kSymMinN up: the symmetric matrix-core kernel (variant 14),
-//     15% ahead of the one-sided one at 2^18 and 23-25% at 2^20 and 2^21,
-//     while its memory cap still allows kSymMinChunks chunks;
+//   * FP64 from kSymMinN up: the symmetric matrix-core kernel (variant 14,
+//     15% ahead of the one-sided one at 2^18 and 23-25% at 2^20 and 2^21),
+//     from kSymQuadMinN in its j-quad layout (variant 30, a further 3% at
+//     2^19, 6.5% at 2^20 and 8% at 2^21), while its memory cap still allows
+//     kSymMinChunks chunks;
 //   * mixed from kSymMinN up: the symmetric mixed kernel (variant 10),
 //     1.31x the one-sided one at 2^18 and 1.45x at 2^21 (FP64
 //     accumulation), under the same chunk cap;
@@ -265,7 +274,7 @@ steps_tile choose_tile(const steps_ctx *c, int64_t n) {
     t.tj = 256;
     t.variant = steps::kVarCull | steps::kVarMfma;
     if (n >= kSymMinN && sym_chunks(n) >= kSymMinChunks) {
-      t.variant |= steps::kVarSym;
+      t.variant |= steps::kVarSym | (n >= kSymQuadMinN ? steps::kVarQuad : 0);
     }
   } else {
     int r = f64 ? 4 : 2;
@@ -1847,12 +1856,12 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
     }
     cands.assign(1, R.v);  // nothing for STEPS_BATCH_AUTOTUNE to choose
   } else {
-    // default: FP64 r=4 without the e^2 term, mixed r=2 (the single-run
-    // tuning)
+    // default: FP64 r=4 without the e^2 term; mixed: the symmetric kernel
+    // with r = 4 (the fastest at the size of workload 4)
     for (const auto *v : cands) {
       const bool want = R.cls == steps::kClassF64
                             ? (v->r == 4 && v->variant == 3)
-                            : v->r == 2;
+                            : (v->r == 4 && batch_is_sym(v));
       if (want) R.v = v;
     }
     if (!R.v) R.v = cands.front();
@@ -1968,7 +1977,23 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
   BATCH_TRY(hipStreamSynchronize(s), "upload");  // host vectors outlive the copies
   BATCH_TRY(batch_resort(R), "ensemble sort");
 
-  // first forces, optionally timing every candidate kernel
+  // first forces, optionally timing every candidate kernel (once per
+  // precision class and list of member sizes on this context)
+  uint64_t sizes_hash = 1469598103934665603ull;  // FNV-1a over the sizes
+  for (int a = 0; a < A; ++a) {
+    sizes_hash = (sizes_hash ^ (uint64_t)(soff[a + 1] - soff[a])) * 1099511628211ull;
+  }
+  const std::pair<int, uint64_t> tune_key{R.cls, sizes_hash};
+  int bcount = 0;
+  const steps::BatchVariant *btable = steps::batch_variants(&bcount);
+  if ((b->flags & STEPS_BATCH_AUTOTUNE) && cands.size() > 1) {
+    for (const auto &e : c->batch_tuned) {
+      if (e.first == tune_key) {
+        R.v = &btable[e.second];
+        cands.assign(1, R.v);
+      }
+    }
+  }
   if ((b->flags & STEPS_BATCH_AUTOTUNE) && cands.size() > 1) {
     hipEvent_t t0 = nullptr, t1 = nullptr;
     BATCH_TRY(hipEventCreate(&t0), "hipEventCreate");
@@ -1994,6 +2019,7 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     R.v = win;
+    c->batch_tuned.push_back({tune_key, (int)(win - btable)});
   }
   BATCH_TRY(upload_layout(R, batch_layout(soff, R.v->r, R.v->tj, batch_is_sym(R.v))),
             "layout");

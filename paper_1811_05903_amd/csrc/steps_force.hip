@@ -906,11 +906,15 @@ __device__ __forceinline__ void sym_block_f64_q(
       // a wave past the end of the chunk: nothing on either side
       for (int k = l; k < 3 * TJ; k += 64) jb[k] = 0.0;
     } else if (use_mfma) {
+      // each group's operands are read one group ahead
+      double bgn = gT[l], cjn = qT[l & 15], bjn = bT[l];
 #pragma unroll 1
       for (int G = 0; G < TJ / 16; ++G) {
-        const double bg = gT[64 * G + l];
-        const double cj = qT[16 * G + (l & 15)];
-        const double bj = bT[64 * G + l];
+        const double bg = bgn, cj = cjn, bj = bjn;
+        const int Gn = min(G + 1, TJ / 16 - 1);
+        bgn = gT[64 * Gn + l];
+        cjn = qT[16 * Gn + (l & 15)];
+        bjn = bT[64 * Gn + l];
         double aj = 0.0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
