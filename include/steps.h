@@ -213,6 +213,23 @@ int steps_forces_ctx(steps_ctx *ctx, const double *pos, const double *mass,
  * (null stream, STEPS_FP64). */
 int steps_forces(const double *pos, const double *mass, const double *soft,
                  int64_t n, double *acc);
+/* Allocation-free steps_forces, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  FP64, same result as steps_forces up to summation
+ * order (the one-sided kernels; <= 1e-12 relative to the exact sum), on the
+ * device that holds pos, enqueued on `stream` (a hipStream_t; NULL = the
+ * null stream) and not waited for.  Arguments as steps_forces, validated
+ * before anything is enqueued; n above 262144 is STEPS_E_INVAL.  It calls no
+ * allocating routine: its scratch (spatial sort, tile boxes, j-split
+ * partial sums) is one fixed 64 MiB device array per GPU, held from the
+ * library's load until the process ends.  Every call on a GPU shares that
+ * array, so calls that overlap on one GPU (different streams not ordered by
+ * the caller, or threads) race; calls ordered on one stream are safe.
+ * Nothing in the array needs to start at zero: each call writes every word
+ * it reads. */
+int steps_forces_noalloc(const double *pos, const double *mass,
+                         const double *soft, int64_t n, double *acc,
+                         void *stream);
 
 /* Autotuner: time the compiled force kernels of the context's precision on
  * these arrays -- i-particles per lane r in {1, 2, 4}, both the culled

@@ -58,7 +58,8 @@ EXPORTS = (
     "steps_ctx_set_periodic",
     "steps_ctx_get_tile",
     "steps_sync", "steps_ctx_force_timing", "steps_autotune", "steps_forces_ctx",
-    "steps_forces", "steps_potential_ctx", "steps_potential",
+    "steps_forces", "steps_forces_noalloc", "steps_potential_ctx",
+    "steps_potential",
     "steps_step_ctx", "steps_step", "steps_energy_ctx", "steps_energy",
     "steps_kinetic_ctx", "steps_kinetic", "steps_adaptive_dt_ctx",
     "steps_adaptive_dt", "steps_run_adaptive_ctx",
@@ -165,6 +166,7 @@ def load():
             "steps_autotune": ([vp, vp, vp, vp, i64, vp, pt], i32),
             "steps_forces_ctx": ([vp, vp, vp, vp, i64, vp], i32),
             "steps_forces": ([vp, vp, vp, i64, vp], i32),
+            "steps_forces_noalloc": ([vp, vp, vp, i64, vp, vp], i32),
             "steps_potential_ctx": ([vp, vp, vp, vp, i64, vp], i32),
             "steps_potential": ([vp, vp, vp, i64, vp], i32),
             "steps_step_ctx": ([vp, vp, vp, vp, vp, i64, vp, d, d, pc], i32),
@@ -356,6 +358,21 @@ def steps_forces(pos, mass, soft, acc=None, ctx: Context | None = None):
             _dev(soft, "soft", (n,)), n, _dev(acc, "acc", (3, n)))
     c.bind_stream()
     _check(c._lib.steps_forces_ctx(c.handle, *args))
+    return acc
+
+
+def steps_forces_noalloc(pos, mass, soft, acc, stream=None):
+    """acc <- S(pos) through the allocation-free entry point (FP64, fixed
+    device scratch, n <= 262144; see steps.h), enqueued on `stream` (a torch
+    stream; default: the current one).  acc must be allocated by the caller.
+    Returns acc."""
+    import torch
+    n = _n_of(mass)
+    s = stream if stream is not None else torch.cuda.current_stream(pos.device)
+    args = (_dev(pos, "pos", (3, n)), _dev(mass, "mass", (n,)),
+            _dev(soft, "soft", (n,)), n, _dev(acc, "acc", (3, n)),
+            ctypes.c_void_p(s.cuda_stream))
+    _check(load().steps_forces_noalloc(*args))
     return acc
 
 

@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsteps.so")
 
 SOURCES = ["steps_force.hip", "steps_sort.hip", "steps_batch.hip",
-           "steps_kernels.hip", "steps_periodic.hip",
+           "steps_kernels.hip", "steps_periodic.hip", "steps_noalloc.hip",
            "steps_api.cpp", "steps_cosmo.cpp"]
 
 HIPCC_FLAGS = [

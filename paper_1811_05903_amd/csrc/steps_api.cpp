@@ -694,6 +694,68 @@ int check_force_args(steps_ctx *c, const double *pos, const double *mass,
                               out_name);
 }
 
+// Allocation-free pair sum (steps_forces_noalloc): largest n, and the plan
+// of the fixed scratch for one call.  The launch shape is the one-sided FP64
+// choice of choose_tile (the symmetric kernels' partial sums grow as
+// n^2 / chunk and do not fit a fixed buffer), with its j-split lowered
+// until the partial sums fit beside the sort scratch.
+constexpr int64_t kNoAllocMaxN = 262144;
+
+struct NoAllocPlan {
+  steps_tile t = {0, 0, 0, 0};
+  int chunk = 0, js = 1;
+  size_t cub_bytes = 0;
+  size_t o_box = 0, o_bpart = 0, o_k0 = 0, o_k1 = 0, o_v0 = 0, o_v1 = 0,
+         o_cub = 0, o_info = 0, o_soa = 0, o_part = 0, total = 0;
+};
+
+int plan_noalloc(int n, hipStream_t s, NoAllocPlan *P) {
+  steps_tile t;
+  int r = 4;
+  if (n >= kMfmaMinN) {
+    t = steps_tile{1, 256, 0, steps::kVarCull | steps::kVarMfma};
+  } else {
+    while (r > 1 && (n + 256LL * r - 1) / (256LL * r) < 256) r /= 2;
+    t = steps_tile{r, variant_tj(steps::kClassF64, r), 0,
+                   n >= kSortMinN ? steps::kVarCull | steps::kVarNoE2 : 0};
+  }
+  const bool cull = (t.variant & steps::kVarCull) != 0;
+  hipError_t e = steps::sort_pairs(nullptr, &P->cub_bytes, nullptr, nullptr,
+                                   nullptr, nullptr, n, s);
+  if (e != hipSuccess) return hip_fail(e, "radix sort size query");
+  int want = heuristic_jsplit(steps::kClassF64, n, t.r, t.tj, t.variant);
+  for (;;) {
+    int chunk = 0, js = 1;
+    split_j(n, t.tj, want, &chunk, &js);
+    Carve cv;
+    if (cull) {
+      P->o_box = cv.take(6 * sizeof(double));
+      P->o_bpart = cv.take((size_t)steps::bbox_blocks(n) * 6 * sizeof(double));
+      P->o_k0 = cv.take((size_t)n * 8);
+      P->o_k1 = cv.take((size_t)n * 8);
+      P->o_v0 = cv.take((size_t)n * 4);
+      P->o_v1 = cv.take((size_t)n * 4);
+      P->o_cub = cv.take(P->cub_bytes);
+      P->o_info = cv.take((size_t)((n + t.tj - 1) / t.tj) * 8 * sizeof(double));
+      P->o_soa = cv.take(5 * (size_t)n * sizeof(double));
+    }
+    P->o_part = cv.take(cull || js > 1 ? (size_t)js * 3 * (size_t)n * sizeof(double) : 0);
+    if (cv.off <= steps::kNoAllocScratchBytes) {
+      t.jsplit = js;
+      P->t = t;
+      P->chunk = chunk;
+      P->js = js;
+      P->total = cv.off;
+      return STEPS_OK;
+    }
+    if (want == 1) break;
+    want = std::max(1, want / 2);
+  }
+  return fail(STEPS_E_INVAL,
+              "n = %d needs more than the %zu bytes of fixed scratch", n,
+              (size_t)steps::kNoAllocScratchBytes);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1026,6 +1088,88 @@ int steps_forces(const double *pos, const double *mass, const double *soft,
   steps_ctx *c = default_ctx(&rc);
   if (!c) return rc;
   return steps_forces_ctx(c, pos, mass, soft, n, acc);
+}
+
+int steps_forces_noalloc(const double *pos, const double *mass,
+                         const double *soft, int64_t n, double *acc,
+                         void *stream) {
+  int rc = check_n(n);
+  if (rc || n == 0) return rc;
+  if (n > kNoAllocMaxN) {
+    return fail(STEPS_E_INVAL,
+                "n = %lld exceeds the allocation-free limit %lld",
+                (long long)n, (long long)kNoAllocMaxN);
+  }
+  if (!pos) return fail(STEPS_E_INVAL, "pos is NULL");
+  hipPointerAttribute_t at;
+  hipError_t e = hipPointerGetAttributes(&at, pos);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(STEPS_E_INVAL, "pos (%p) is not memory known to HIP", pos);
+  }
+  int device = at.device;
+  if (at.type != hipMemoryTypeDevice && (e = hipGetDevice(&device)) != hipSuccess) {
+    return hip_fail(e, "hipGetDevice");
+  }
+  DeviceGuard g(device);
+  if ((rc = check_force_args_dev(device, pos, mass, soft, n, acc,
+                                 3 * (size_t)n * sizeof(double), "acc"))) {
+    return rc;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  void *scr = nullptr;
+  if ((e = steps::noalloc_scratch(device, &scr)) != hipSuccess) {
+    return hip_fail(e, "fixed scratch address");
+  }
+  NoAllocPlan P;
+  const int ni = (int)n;
+  if ((rc = plan_noalloc(ni, s, &P))) return rc;
+  const steps::ForceVariant *v = steps::find_force_variant(
+      steps::kClassF64, P.t.r, P.t.tj, P.t.variant);
+  if (!v) return fail(STEPS_E_INVAL, "no compiled force kernel for n = %d", ni);
+  char *base = (char *)scr;
+  const bool cull = (P.t.variant & steps::kVarCull) != 0;
+  steps::ForceLaunch L;
+  L.n = ni;
+  L.jchunk = P.chunk;
+  L.jsplit = P.js;
+  L.out = cull || P.js > 1 ? (double *)(base + P.o_part) : acc;
+  const int *perm = nullptr;
+  if (cull) {
+    auto *k0 = (unsigned long long *)(base + P.o_k0);
+    auto *k1 = (unsigned long long *)(base + P.o_k1);
+    int *v0 = (int *)(base + P.o_v0), *v1 = (int *)(base + P.o_v1);
+    double *box = (double *)(base + P.o_box);
+    double *sorted = (double *)(base + P.o_soa);
+    size_t cub_bytes = P.cub_bytes;
+    if ((e = steps::launch_bbox(pos, ni, (double *)(base + P.o_bpart), box, s)) != hipSuccess ||
+        (e = steps::launch_morton(pos, ni, box, k0, v0, s)) != hipSuccess ||
+        (e = steps::sort_pairs(base + P.o_cub, &cub_bytes, k0, k1, v0, v1, ni, s)) !=
+            hipSuccess ||
+        (e = steps::launch_gather(pos, mass, soft, v1, ni, sorted, nullptr, s)) !=
+            hipSuccess ||
+        (e = steps::launch_tile_info_f64(sorted, ni, P.t.tj,
+                                         (double *)(base + P.o_info), s)) != hipSuccess) {
+      return hip_fail(e, "spatial sort launch");
+    }
+    perm = v1;
+    L.pos = sorted;
+    L.mass = sorted + 3 * (size_t)ni;
+    L.soft = sorted + 4 * (size_t)ni;
+    L.tinfo = (const double *)(base + P.o_info);
+  } else {
+    L.pos = pos;
+    L.mass = mass;
+    L.soft = soft;
+  }
+  if ((e = v->launch(L, s)) != hipSuccess) return hip_fail(e, "force kernel launch");
+  if (cull) {
+    e = steps::launch_reduce_scatter(L.out, P.js, ni, perm, acc, s);
+  } else if (P.js > 1) {
+    e = steps::launch_reduce_partials(L.out, P.js, ni, acc, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "reduce kernel launch");
+  return STEPS_OK;
 }
 
 int steps_potential_ctx(steps_ctx *c, const double *pos, const double *mass,

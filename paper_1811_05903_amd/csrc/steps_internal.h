@@ -182,6 +182,12 @@ hipError_t launch_energy(const double *pos, const double *vel,
                          const double *mass, const double *phi, int n,
                          double *part, double *out, hipStream_t s);
 
+// ---- fixed scratch of steps_forces_noalloc (steps_noalloc.hip) ---------
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+// This device's copy of the fixed scratch array (kNoAllocScratchBytes),
+// its address looked up once per device.
+hipError_t noalloc_scratch(int device, void **out);
+
 // FP32 shadow [5][n] (x, y, z, m, h) from the FP64 inputs.
 hipError_t launch_shadow(const double *pos, const double *mass,
                          const double *soft, int n, float *shadow,
