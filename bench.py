@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-member ensemble comparison")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched 64-member ensemble (no "
+                         "sequential comparison; for profiling its kernels)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the single-thread oracle sample")
     ap.add_argument("--tile", default=None, metavar="R,TJ,JSPLIT,VARIANT",
@@ -258,6 +261,10 @@ def main():
 
     if args.workload == 5:
         print(json.dumps(workload5(st, dev, args)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps({"batch": batch_leg(st, dev, args.batch_steps,
+                                             sequential=False)}), flush=True)
         return
 
     ps = synth.config(args.workload)
@@ -653,7 +660,7 @@ def periodic_leg(st, dev):
     return out
 
 
-def batch_leg(st, dev, nsteps, members=64, n_scale=1.0):
+def batch_leg(st, dev, nsteps, members=64, n_scale=1.0, sequential=True):
     """Workload 4: 64 members, N_b ~ U{8192..131072}, Omega_m ~ U[0.25,
     0.35] flat, 100 log steps a 0.02 -> 1.0, mixed precision: one
     steps_batch_run (persistent kernel, graph-replayed step, autotuned)
@@ -690,6 +697,12 @@ def batch_leg(st, dev, nsteps, members=64, n_scale=1.0):
     tile = st.steps_batch_tile(ctx)
     log("ensemble: %d members, N=%d, %d steps batched in %.2f s (%.3e pairs/s), tile %s"
         % (len(members), offs[-1], nsteps, t_batch, pairs / t_batch, tile))
+    if not sequential:
+        ctx.close()
+        return {"members": len(members), "n_total": int(offs[-1]),
+                "steps": nsteps, "pairs_per_step": pairs / nsteps,
+                "batched_s": t_batch, "batched_pairs_per_s": pairs / t_batch,
+                "tile": tile}
     # sequential: each member alone through steps_step
     per = [(dev(m.pos), dev(m.vel), dev(m.mass), dev(m.soft)) for m in members]
     grids = [m.a_grid() for m in members]

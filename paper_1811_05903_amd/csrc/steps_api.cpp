@@ -30,8 +30,9 @@ constexpr int64_t kMaxN = int64_t(1) << 30;
 constexpr int64_t kSortMinN = 32768;
 constexpr int64_t kMfmaMinN = 131072;
 constexpr int64_t kSymMinN = 262144;
-// below this many chunks (the memory cap binds from N ~ 2^22.5) the units
-// no longer fill the device evenly and the one-sided kernel is used
+// below this many chunks (the memory cap binds from N ~ 2^22 and leaves
+// fewer than 64 chunks from N ~ 2^23.5) the units no longer fill the device
+// evenly and the one-sided kernel is used
 constexpr int kSymMinChunks = 64;
 constexpr int64_t kMixedSymR4MinN = 524288;
 // from here the FP64 symmetric kernel takes its j-quad layout (variant 30):
@@ -200,13 +201,17 @@ int variant_tj(int cls, int r) {
 // R <= s, of chunk pairs, one workgroup each).  Units are equal, so the
 // last round of workgroups runs part-empty; measured on MI355X, more and
 // smaller units win until chunks of about 1024 particles (N = 2^18: 34.9 ms
-// at Q = 64, 32.5 ms at Q = 256; N = 2^20: 458 ms from Q = 160 on).  So:
-// the largest Q up to 192 with chunks of at least 1024 particles and the
-// partial sums (24 n Q + 48 C Q (Q - 1) / 2 bytes) under 16 GiB.
+// at Q = 64, 32.5 ms at Q = 256; N = 2^20: 458 ms from Q = 160 on; N =
+// 2^21: 1547 against 1563 ms (FP64) and 751 against 761 ms (mixed) at
+// Q = 256 against 174).  So: the largest Q up to 192 (256 from 2^20, where
+// the larger reduction no longer outweighs the gain) with chunks of at
+// least 1024 particles and the partial sums (24 n Q + 48 C Q (Q - 1) / 2
+// bytes, about 48 Q n) under 32 GiB.
 int sym_chunks(int64_t n) {
-  const double cap = 16.0 * (1ull << 30);
+  const double cap = 32.0 * (1ull << 30);
+  const int qmax = n >= (int64_t(1) << 20) ? 256 : 192;
   int best = 1;
-  for (int want = 1; want <= 192; ++want) {
+  for (int want = 1; want <= qmax; ++want) {
     int64_t c = (n + want - 1) / want;
     c = std::max<int64_t>(256, (c + 255) / 256 * 256);
     const int q = (int)((n + c - 1) / c);

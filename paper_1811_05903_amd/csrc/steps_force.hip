@@ -1430,18 +1430,25 @@ __device__ __forceinline__ void sym_block_mixed(
     float tx[R], ty[R], tz[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) tx[r] = ty[r] = tz[r] = 0.0f;
-    if (live) {
-      for (int q = 0; q < TJ; q += 64) {
-        if (far) {
+    if (live && far) {
+      // two parts of 64 j per step (j and j + 64 of the same rotation):
+      // one address computation and one loop step serve 2 R pairs
+      static_assert(TJ % 128 == 0, "the far loop takes parts in pairs");
+      for (int q = 0; q < TJ; q += 128) {
 #pragma unroll 2
-          for (int t = 0; t < 64; ++t) {
-            const int jj = q + ((l + t) & 63);
-            const float4 p = tpos[jj];
-            // this j's running sums, read before the pair arithmetic that
-            // hides their latency (plain read-modify-write: one lane per
-            // address within a step; the word lane l writes here is read by
-            // lane l - 1 in the next step, ordered by lds_step_fence below)
-            float jx = jw[jj], jy = jw[TJ + jj], jz = jw[2 * TJ + jj];
+        for (int t = 0; t < 64; ++t) {
+          const int jj = q + ((l + t) & 63);
+          const float4 pa = tpos[jj], pb = tpos[jj + 64];
+          // these j's running sums, read before the pair arithmetic that
+          // hides their latency (plain read-modify-write: one lane per
+          // address within a step; the words lane l writes here are read by
+          // lane l - 1 in the next step, ordered by lds_step_fence below)
+          float ax_ = jw[jj], ay_ = jw[TJ + jj], az_ = jw[2 * TJ + jj];
+          float bx_ = jw[jj + 64], by_ = jw[TJ + jj + 64], bz_ = jw[2 * TJ + jj + 64];
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const float4 p = h ? pb : pa;
+            float jx = h ? bx_ : ax_, jy = h ? by_ : ay_, jz = h ? bz_ : az_;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
               const float dx = p.x - xi[r], dy = p.y - yi[r], dz = p.z - zi[r];
@@ -1463,12 +1470,24 @@ __device__ __forceinline__ void sym_block_mixed(
               jy = fmaf(wj, dy, jy);
               jz = fmaf(wj, dz, jz);
             }
-            jw[jj] = jx;
-            jw[TJ + jj] = jy;
-            jw[2 * TJ + jj] = jz;
-            lds_step_fence();
+            if (h) {
+              bx_ = jx; by_ = jy; bz_ = jz;
+            } else {
+              ax_ = jx; ay_ = jy; az_ = jz;
+            }
           }
-        } else {
+          jw[jj] = ax_;
+          jw[TJ + jj] = ay_;
+          jw[2 * TJ + jj] = az_;
+          jw[jj + 64] = bx_;
+          jw[TJ + jj + 64] = by_;
+          jw[2 * TJ + jj + 64] = bz_;
+          lds_step_fence();
+        }
+      }
+    } else if (live) {
+      for (int q = 0; q < TJ; q += 64) {
+        {
           // softening tested per pair (coincident pairs take the softened
           // branch, which gives 0)
 #pragma unroll 2
