@@ -381,7 +381,7 @@ def force_kernel_name(precision, tile):
     if precision != "fp64":
         return "k_force_mixed_sym" if tile["variant"] & 8 else "k_force_mixed"
     if tile["variant"] & 8:
-        return "k_force_f64_sym"
+        return "k_force_f64_symq" if tile["variant"] & 16 else "k_force_f64_sym"
     return "k_force_f64_mfma" if tile["variant"] & 4 else "k_force_f64"
 
 
