@@ -723,8 +723,9 @@ def batch_leg(st, dev, nsteps, members=64, n_scale=1.0, sequential=True):
             "batched_s": t_batch, "batched_pairs_per_s": pairs / t_batch,
             "sequential_s": t_seq, "sequential_pairs_per_s": pairs / t_seq,
             "speedup": t_seq / t_batch, "tile": tile,
-            "note": "batched time includes the in-library sort, autotune "
-                    "and initial force evaluation"}
+            "note": "batched time includes the in-library sort and the "
+                    "initial force evaluation; the kernel is the one the "
+                    "warm-up run's autotune chose (kept in the context)"}
 
 
 def binned_errors(err, kappa, radius, nbins=3):
