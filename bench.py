@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--workload", type=int, default=3, choices=[2, 3, 5])
     ap.add_argument("--no-glass", action="store_true",
                     help="skip the glass-relaxation and periodic legs")
+    ap.add_argument("--no-li-study", action="store_true",
+                    help="workload 5: skip the Layzer-Irvine step-convergence "
+                         "study at N = 2^17")
     ap.add_argument("--li-study-only", action="store_true",
                     help="workload 5: only the Layzer-Irvine step-convergence "
                          "study at N = 2^17")
@@ -495,7 +498,7 @@ def workload5(st, dev, args):
     import numpy as np
     import torch
     import synth
-    study = li_convergence(st, dev)
+    study = None if args.no_li_study else li_convergence(st, dev)
     if args.li_study_only:
         return {"layzer_irvine_convergence": study}
     ps = synth.config(5)
