@@ -859,7 +859,9 @@ __device__ __forceinline__ void sym_block_f64_q(
 
   for (int jt = jbeg; jt < jend; jt += TJ) {
     const double *ti = tinfo + (size_t)((jt - jbeg) / TJ) * 8;
-    __syncthreads();
+    // No barrier before staging: every wave finished reading the previous
+    // tile before the barrier that precedes the previous tile's j-side sum,
+    // and that sum reads only jbuf, which staging does not touch.
     {
       const int k = tid;
       const int j = min(jt + k, jend - 1);
@@ -1417,14 +1419,18 @@ __device__ __forceinline__ void sym_block_mixed(
   wave_box<R, float>(xi, yi, zi, hi, valid, wb);
 
   for (int jt = jbeg; jt < jend; jt += TJ) {
-    __syncthreads();
+    // No barrier before staging: every wave finished reading the previous
+    // tile before the barrier that precedes the previous tile's j-side sum,
+    // and that sum reads only jl.  A wave clears its own j-sums after the
+    // staging barrier, when no thread is still reading them.
     {
       const int j = min(jt + tid, jend - 1);
       tpos[tid] = float4{X[j], Y[j], Z[j], (jt + tid < jend) ? M[j] : 0.0f};
       tsoft[tid] = H[j];
     }
-    for (int k = l; k < 3 * TJ; k += 64) jw[k] = 0.0f;
     __syncthreads();
+    for (int k = l; k < 3 * TJ; k += 64) jw[k] = 0.0f;
+    lds_step_fence();  // the zeros before the rotation's first loads
 
     const bool far = tile_is_far(tinfo + (size_t)((jt - jbeg) / TJ) * 8, wb);
     float tx[R], ty[R], tz[R];
