@@ -296,7 +296,10 @@ __device__ __forceinline__ void force_block_f64_mfma(
     const double *__restrict__ pos, const double *__restrict__ mass,
     const double *__restrict__ soft, int stride, int i0, int iend, int jbeg,
     int jend, const double *__restrict__ tinfo, double *__restrict__ out,
-    double2 *tile, double *gram, double *bmat) {
+    double2 *tile, double *gram, double *bmat, int ostride = -1,
+    int obase = 0) {
+  // results go to out[c * ostride + i - obase] (ostride < 0: stride)
+  const size_t os = ostride < 0 ? (size_t)stride : (size_t)ostride;
   const int tid = threadIdx.x;
   const int l = tid & 63;
   const int wbase = i0 + (tid >> 6) * 64;
@@ -457,7 +460,7 @@ __device__ __forceinline__ void force_block_f64_mfma(
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int id = wbase + 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
-    if (cc < 3 && id < iend) out[(size_t)cc * stride + id] = sum[r] + cmp[r];
+    if (cc < 3 && id < iend) out[(size_t)cc * os + id - obase] = sum[r] + cmp[r];
   }
 }
 
@@ -793,9 +796,12 @@ __device__ __forceinline__ void sym_block_f64_q(
     int jend, const double *__restrict__ tinfo,
     const double *__restrict__ iinfo, double *__restrict__ out,
     double *__restrict__ jacc, int chunk, bool first, double2 *tile,
-    double *gT, double *qT, double *bT, double *jbuf) {
+    double *gT, double *qT, double *bT, double *jbuf, int ostride = -1,
+    int obase = 0) {
   static_assert(TJ == kBlock, "one thread per tile particle in the j-side sum");
   constexpr int NQ = 16;  // i-quads of a wave
+  // i-side results go to out[c * ostride + i - obase] (ostride < 0: stride)
+  const size_t os = ostride < 0 ? (size_t)stride : (size_t)ostride;
   const int tid = threadIdx.x;
   const int l = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1053,7 +1059,7 @@ __device__ __forceinline__ void sym_block_f64_q(
     const double ui = cc < 3 ? Pc[min(id, last)] - ccb : 0.0;
     const double f = fma(-ui, quad_bcast3(part[r]), part[r]);
     two_sum_add(sum[r], cmp[r], cc < 3 ? f : 0.0);
-    if (cc < 3 && id < iend) out[(size_t)cc * stride + id] = sum[r] + cmp[r];
+    if (cc < 3 && id < iend) out[(size_t)cc * os + id - obase] = sum[r] + cmp[r];
   }
 }
 
@@ -1753,6 +1759,43 @@ __global__ __launch_bounds__(kBlock) void k_batch_force_mixed_sym(
   }
 }
 
+// Symmetric ensemble kernel, FP64: the units and slots of
+// k_batch_force_mixed_sym, each off-diagonal unit run by the j-quad block of
+// k_force_f64_symq, each diagonal unit by the one-sided matrix-core block.
+// Tiles of 256 run from each member's start, so the tile of an i-block is
+// that of the unit's j-range shifted by (ibeg - jbeg) / 256.
+template <int TJ>
+__global__ __launch_bounds__(kBlock, 2) void k_batch_force_f64_sym(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ soft, int stride, const int4 *__restrict__ units,
+    const int *__restrict__ tbase, const int *__restrict__ uslot, int nunits,
+    const double *__restrict__ tinfo, double *__restrict__ usum, int chunk) {
+  __shared__ double2 tile[3 * TJ];
+  __shared__ double gram[4 * TJ];
+  __shared__ double bmat[4 * TJ];
+  __shared__ double qj[TJ];
+  __shared__ double jbuf[4 * TJ * 3];
+  const int u = blockIdx.x;
+  if (u >= nunits) return;
+  const int4 w = units[u];
+  const double *ti = tinfo + (size_t)tbase[u] * 8;
+  double *slot = usum + (size_t)uslot[u] * 9 * (size_t)chunk;
+  if (w.x == w.z) {
+    for (int i0 = w.x; i0 < w.y; i0 += kBlock) {
+      force_block_f64_mfma<TJ>(pos, mass, soft, stride, i0, w.y, w.z, w.w, ti,
+                               slot, tile, gram, bmat, chunk, w.x);
+    }
+    return;
+  }
+  const double *ib = ti + (ptrdiff_t)((w.x - w.z) / TJ) * 8;
+  for (int i0 = w.x; i0 < w.y; i0 += kBlock) {
+    sym_block_f64_q<TJ>(pos, mass, soft, stride, i0, w.y, w.z, w.w, ti,
+                        ib + (size_t)((i0 - w.x) / TJ) * 8, slot,
+                        slot + 3 * (size_t)chunk, chunk, i0 == w.x, tile, gram,
+                        qj, bmat, jbuf, chunk, w.x);
+  }
+}
+
 // acc[d][p] for arena slot p of member a = mid[p], in chunk k of that
 // member: the i-side sums of units (k, t), t = k .. Q_a - 1, then the j-side
 // (value, error) accumulators of units (R, k), R < k, compensated, in that
@@ -1898,6 +1941,17 @@ hipError_t launch_batch_f64_mfma(const BatchLaunch &L, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_batch_f64_sym(const BatchLaunch &L, hipStream_t s) {
+  if (!L.usum || L.chunk <= 0 || L.chunk % 256 != 0 || L.nitems < 0) {
+    return hipErrorInvalidValue;
+  }
+  if (L.nitems == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_batch_force_f64_sym<256>), dim3(L.nitems), dim3(kBlock),
+                     0, s, L.pos, L.mass, L.soft, L.stride, L.items, L.tbase,
+                     L.islot, L.nitems, L.tinfo, L.usum, L.chunk);
+  return hipGetLastError();
+}
+
 template <int R>
 hipError_t launch_batch_mixed_sym(const BatchLaunch &L, hipStream_t s) {
   if (!L.usum || L.chunk <= 0 || L.chunk % 256 != 0 || L.nitems < 0) {
@@ -1967,6 +2021,7 @@ const BatchVariant kBatchVariants[] = {
     {kClassF64, 4, 128, 2, launch_batch_f64<4, 128, true>},
     {kClassF64, 4, 128, 3, launch_batch_f64<4, 128, false>},
     {kClassF64, 1, 128, 6, launch_batch_f64_mfma<128>},
+    {kClassF64, 1, 256, 30, launch_batch_f64_sym},
     {kClassMixed, 1, 128, 2, launch_batch_mixed<1, 128>},
     {kClassMixed, 2, 256, 2, launch_batch_mixed<2, 256>},
     {kClassMixed, 4, 256, 2, launch_batch_mixed<4, 256>},

@@ -169,7 +169,7 @@ def test_batch_forces_match_oracle(st, prec):
 # every FP64 ensemble kernel, forced through the context's tile: (r, tj,
 # variant) as listed by the library
 @pytest.mark.parametrize("shape", [(2, 128, 2), (2, 128, 3), (4, 128, 2),
-                                   (4, 128, 3), (1, 128, 6)])
+                                   (4, 128, 3), (1, 128, 6), (1, 256, 30)])
 def test_batch_fp64_kernel_matches_oracle(st, shape):
     members = _members()
     ctx = st.Context(0, precision="fp64")
@@ -210,18 +210,42 @@ def test_batch_mixed_kernel_matches_oracle(st, prec, shape):
             (prec, shape, b, np.median(err), err.max())
 
 
-def test_batch_symmetric_graph_bitwise_and_repeatable(st):
-    # the symmetric ensemble kernel: graph replay equals launches, bitwise,
+@pytest.mark.parametrize("prec,shape", [("mixed", (4, 256, 10)), ("fp64", (1, 256, 30))])
+def test_batch_symmetric_graph_bitwise_and_repeatable(st, prec, shape):
+    # the symmetric ensemble kernels: graph replay equals launches, bitwise,
     # and two runs agree bitwise
     members = _members()
     out = []
     for flags in (st.STEPS_BATCH_GRAPH, 0, st.STEPS_BATCH_GRAPH):
-        ctx = st.Context(0, precision="mixed")
-        ctx.set_tile(4, 256, 1, 10)
+        ctx = st.Context(0, precision=prec)
+        ctx.set_tile(shape[0], shape[1], 1, shape[2])
         out.append(_run(st, members, flags, ctx=ctx))
         ctx.close()
     for x, y, z in zip(out[0][1:4], out[1][1:4], out[2][1:4]):
         assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+def test_batch_fp64_symmetric_trajectories_match_oracle(st):
+    # the FP64 symmetric ensemble kernel over the whole run, every member
+    # against the oracle's own integration (as the default-kernel test)
+    members = _members()
+    ctx = st.Context(0, precision="fp64")
+    ctx.set_tile(1, 256, 1, 30)
+    status, p, v, acc, offs = _run(st, members, st.STEPS_BATCH_GRAPH, ctx=ctx)
+    ctx.close()
+    assert status == [0] * len(members)
+    for b, m in enumerate(members):
+        if m.n == 0:
+            continue
+        oc = oracle.Cosmology(m.cosmo.H0, m.cosmo.omega_m, m.cosmo.omega_l)
+        po, vo, So = oracle.run(m.pos, m.vel, m.mass, m.soft,
+                                _grid(m.a0, m.a1, NSTEPS), oc)
+        sl = slice(offs[b], offs[b + 1])
+        dx = np.linalg.norm(p[:, sl] - po, axis=0) / m.soft
+        assert np.median(dx) < 1e-10 and dx.max() < 1e-7, (b, np.median(dx), dx.max())
+        if m.n > 1:
+            dS = np.linalg.norm(acc[:, sl] - So, axis=0) / np.linalg.norm(So, axis=0)
+            assert np.median(dS) < 1e-10
 
 
 def test_batch_forced_tile_must_name_an_ensemble_kernel(st):

@@ -18,7 +18,8 @@ from gpu_util import dev, host
 pytestmark = pytest.mark.gpu
 
 ROWS = 256
-SHAPES_F64 = [(2, 128, 2), (2, 128, 3), (4, 128, 2), (4, 128, 3), (1, 128, 6)]
+SHAPES_F64 = [(2, 128, 2), (2, 128, 3), (4, 128, 2), (4, 128, 3), (1, 128, 6),
+              (1, 256, 30)]
 # one-sided (variant 2) and symmetric (variant 10: chunk-pair units of each
 # member, one weight per unordered pair) ensemble kernels
 SHAPES_MIXED = [(1, 128, 2), (2, 256, 2), (4, 256, 2), (2, 256, 10), (4, 256, 10)]
