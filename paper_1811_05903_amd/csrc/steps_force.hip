@@ -862,203 +862,217 @@ __device__ __forceinline__ void sym_block_f64_q(
   // this lane's j-side slot in a group of 16 j: j = 16 G + 4 b + jj, b the
   // block, jj = l >> 4, component cc
   const int jslot = (l & 12) + kk;
-
-  for (int jt = jbeg; jt < jend; jt += TJ) {
-    const double *ti = tinfo + (size_t)((jt - jbeg) / TJ) * 8;
-    // No barrier before staging: every wave finished reading the previous
-    // tile before the barrier that precedes the previous tile's j-side sum,
-    // and that sum reads only jbuf, which staging does not touch.
-    {
-      const int k = tid;
-      const int j = min(jt + k, jend - 1);
-      const double mj = (jt + k < jend) ? mass[j] : 0.0;
-      const double xj = X[j], yj = Y[j], zj = Z[j];
-      tile[3 * k] = double2{xj, yj};
-      tile[3 * k + 1] = double2{zj, mj};
-      tile[3 * k + 2] = double2{soft[j], 0.0};
-      const double ux = xj - cb[0], uy = yj - cb[1], uz = zj - cb[2];
-      const int G = k >> 4, jl = k & 15;
-      gT[64 * G + jl] = ux;
-      gT[64 * G + 16 + jl] = uy;
-      gT[64 * G + 32 + jl] = uz;
-      gT[64 * G + 48 + jl] = 1.0;
-      qT[k] = fma(uz, uz, fma(uy, uy, ux * ux));
-      const double mm = -1.5 * mj;
-      const int bo = 64 * G + 16 * (jl & 3) + 4 * (jl >> 2);
-      bT[bo] = mm * ux;
-      bT[bo + 1] = mm * uy;
-      bT[bo + 2] = mm * uz;
-      bT[bo + 3] = mm;
-    }
-    const bool jown = jt + tid < jend;
-    const size_t jl = (size_t)(jt + tid - jbeg);
-    __syncthreads();
-
-    const double gxv = fmax(0.0, fmax(ti[0] - wb[3], wb[0] - ti[3]));
-    const double gyv = fmax(0.0, fmax(ti[1] - wb[4], wb[1] - ti[4]));
-    const double gzv = fmax(0.0, fmax(ti[2] - wb[5], wb[2] - ti[5]));
-    const double d2 = gxv * gxv + gyv * gyv + gzv * gzv;
-    const double hs = ti[6] + wb[6];
-    const bool far = d2 > fmax(hs * hs * (1.0 + 1e-6), 1e-30);
-    const double bt =
-        sqrt((0.5 * (ti[0] + ti[3]) - cb[0]) * (0.5 * (ti[0] + ti[3]) - cb[0]) +
-             (0.5 * (ti[1] + ti[4]) - cb[1]) * (0.5 * (ti[1] + ti[4]) - cb[1]) +
-             (0.5 * (ti[2] + ti[5]) - cb[2]) * (0.5 * (ti[2] + ti[5]) - cb[2])) +
-        0.5 * sqrt((ti[3] - ti[0]) * (ti[3] - ti[0]) +
-                   (ti[4] - ti[1]) * (ti[4] - ti[1]) +
-                   (ti[5] - ti[2]) * (ti[5] - ti[2]));
-    const bool sep = far && (aw + bt) <= kSepSym * sqrt(d2);
-    const bool use_mfma = __builtin_amdgcn_readfirstlane((int)sep) != 0;
-
-    if (nw == 0) {
-      // a wave past the end of the chunk: nothing on either side
-      for (int k = l; k < 3 * TJ; k += 64) jb[k] = 0.0;
-    } else if (use_mfma) {
-      // each group's operands are read one group ahead
-      double bgn = gT[l], cjn = qT[l & 15], bjn = bT[l];
-#pragma unroll 1
-      for (int G = 0; G < TJ / 16; ++G) {
-        const double bg = bgn, cj = cjn, bj = bjn;
-        const int Gn = min(G + 1, TJ / 16 - 1);
-        bgn = gT[64 * Gn + l];
-        cjn = qT[16 * Gn + (l & 15)];
-        bjn = bT[64 * Gn + l];
-        double aj = 0.0;
+  // Far i-side fold: add each quad's four j-quad blocks (row rotations),
+  // keep quad q = 4r + b in the lanes of block b, form S = D_c - u_{i,c} D_3
+  // and add it into the compensated running sums; the accumulators restart.
+  // Done every kFoldTiles tiles and at the end of the pass, so that a plain
+  // matrix-core accumulation never spans more than 512 j per block.
+  constexpr int kFoldTiles = 8;
+  auto fold_far = [&]() {
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          const double rr = mfma4(ag[q], bg, cj);
-          const double y = __builtin_amdgcn_rsq(rr);
-          const double y2 = y * y;
-          const double t = fma(rr, y2, -5.0 / 3.0);
-          const double w = (y * y2) * t;  // -(2/3) r^-3 (1 + 3/2 e)
-          aj = mfma4(w, bi[q], aj);
-          acci[q] = mfma4(__shfl(w, tsrc), bj, acci[q]);
-        }
-        // j-side of the group: D_c - u_{j,c} D_3 (D_3 from the quad's lane 3)
-        const double uj = gT[64 * G + 16 * cc + (l & 12) + kk];
-        const double f = fma(-uj, quad_bcast3(aj), aj);
-        if (cc < 3) jb[3 * (16 * G + jslot) + cc] = f;
+    for (int q = 0; q < NQ; ++q) {
+      double v = acci[q];
+      v += row_ror<4>(v);
+      v += row_ror<8>(v);
+      if (((l >> 2) & 3) == (q & 3)) part[q >> 2] = v;
+      acci[q] = 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int id = wbase + 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
+      const double ui = cc < 3 ? Pc[min(id, last)] - ccb : 0.0;
+      const double f = fma(-ui, quad_bcast3(part[r]), part[r]);
+      two_sum_add(sum[r], cmp[r], cc < 3 ? f : 0.0);
+    }
+  };
+
+  for (int jg = jbeg; jg < jend; jg += kFoldTiles * TJ) {
+    const int jgend = min(jend, jg + kFoldTiles * TJ);
+    for (int jt = jg; jt < jgend; jt += TJ) {
+      const double *ti = tinfo + (size_t)((jt - jbeg) / TJ) * 8;
+      // No barrier before staging: every wave finished reading the previous
+      // tile before the barrier that precedes the previous tile's j-side sum,
+      // and that sum reads only jbuf, which staging does not touch.
+      {
+        const int k = tid;
+        const int j = min(jt + k, jend - 1);
+        const double mj = (jt + k < jend) ? mass[j] : 0.0;
+        const double xj = X[j], yj = Y[j], zj = Z[j];
+        tile[3 * k] = double2{xj, yj};
+        tile[3 * k + 1] = double2{zj, mj};
+        tile[3 * k + 2] = double2{soft[j], 0.0};
+        const double ux = xj - cb[0], uy = yj - cb[1], uz = zj - cb[2];
+        const int G = k >> 4, jl = k & 15;
+        gT[64 * G + jl] = ux;
+        gT[64 * G + 16 + jl] = uy;
+        gT[64 * G + 32 + jl] = uz;
+        gT[64 * G + 48 + jl] = 1.0;
+        qT[k] = fma(uz, uz, fma(uy, uy, ux * ux));
+        const double mm = -1.5 * mj;
+        const int bo = 64 * G + 16 * (jl & 3) + 4 * (jl >> 2);
+        bT[bo] = mm * ux;
+        bT[bo + 1] = mm * uy;
+        bT[bo + 2] = mm * uz;
+        bT[bo + 3] = mm;
       }
-    } else {
-      // near block: the direct loops of sym_block_f64 (lane = i, then
-      // lane = j), results in the output layout
-      double tx = 0.0, ty = 0.0, tz = 0.0;
-      if (__builtin_amdgcn_readfirstlane((int)far)) {
-#pragma unroll 4
-        for (int k = 0; k < TJ; ++k) {
-          const double2 a = tile[3 * k], b = tile[3 * k + 1];
-          const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
-          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-          const double w = newton_w64<true>(r2, b.y);
-          tx = fma(w, dx, tx);
-          ty = fma(w, dy, ty);
-          tz = fma(w, dz, tz);
+      const bool jown = jt + tid < jend;
+      const size_t jl = (size_t)(jt + tid - jbeg);
+      __syncthreads();
+
+      const double gxv = fmax(0.0, fmax(ti[0] - wb[3], wb[0] - ti[3]));
+      const double gyv = fmax(0.0, fmax(ti[1] - wb[4], wb[1] - ti[4]));
+      const double gzv = fmax(0.0, fmax(ti[2] - wb[5], wb[2] - ti[5]));
+      const double d2 = gxv * gxv + gyv * gyv + gzv * gzv;
+      const double hs = ti[6] + wb[6];
+      const bool far = d2 > fmax(hs * hs * (1.0 + 1e-6), 1e-30);
+      const double bt =
+          sqrt((0.5 * (ti[0] + ti[3]) - cb[0]) * (0.5 * (ti[0] + ti[3]) - cb[0]) +
+               (0.5 * (ti[1] + ti[4]) - cb[1]) * (0.5 * (ti[1] + ti[4]) - cb[1]) +
+               (0.5 * (ti[2] + ti[5]) - cb[2]) * (0.5 * (ti[2] + ti[5]) - cb[2])) +
+          0.5 * sqrt((ti[3] - ti[0]) * (ti[3] - ti[0]) +
+                     (ti[4] - ti[1]) * (ti[4] - ti[1]) +
+                     (ti[5] - ti[2]) * (ti[5] - ti[2]));
+      const bool sep = far && (aw + bt) <= kSepSym * sqrt(d2);
+      const bool use_mfma = __builtin_amdgcn_readfirstlane((int)sep) != 0;
+
+      if (nw == 0) {
+        // a wave past the end of the chunk: nothing on either side
+        for (int k = l; k < 3 * TJ; k += 64) jb[k] = 0.0;
+      } else if (use_mfma) {
+        // each group's operands are read one group ahead
+        double bgn = gT[l], cjn = qT[l & 15], bjn = bT[l];
+#pragma unroll 1
+        for (int G = 0; G < TJ / 16; ++G) {
+          const double bg = bgn, cj = cjn, bj = bjn;
+          const int Gn = min(G + 1, TJ / 16 - 1);
+          bgn = gT[64 * Gn + l];
+          cjn = qT[16 * Gn + (l & 15)];
+          bjn = bT[64 * Gn + l];
+          double aj = 0.0;
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            const double rr = mfma4(ag[q], bg, cj);
+            const double y = __builtin_amdgcn_rsq(rr);
+            const double y2 = y * y;
+            const double t = fma(rr, y2, -5.0 / 3.0);
+            const double w = (y * y2) * t;  // -(2/3) r^-3 (1 + 3/2 e)
+            aj = mfma4(w, bi[q], aj);
+            acci[q] = mfma4(__shfl(w, tsrc), bj, acci[q]);
+          }
+          // j-side of the group: D_c - u_{j,c} D_3 (D_3 from the quad's lane 3)
+          const double uj = gT[64 * G + 16 * cc + (l & 12) + kk];
+          const double f = fma(-uj, quad_bcast3(aj), aj);
+          if (cc < 3) jb[3 * (16 * G + jslot) + cc] = f;
         }
       } else {
-#pragma unroll 2
-        for (int k = 0; k < TJ; ++k) {
-          const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
-          const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
-          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-          const double h = c.x + hi;
-          double w = newton_w64<true>(r2, b.y);
-          if (r2 <= h * h) w = soft_w64(r2, h, b.y);
-          tx = fma(w, dx, tx);
-          ty = fma(w, dy, ty);
-          tz = fma(w, dz, tz);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int src = 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
-        const double vx = __shfl(tx, src), vy = __shfl(ty, src), vz = __shfl(tz, src);
-        two_sum_add(sum[r], cmp[r],
-                    cc == 0 ? vx : (cc == 1 ? vy : (cc == 2 ? vz : 0.0)));
-      }
-      const bool farw = __builtin_amdgcn_readfirstlane((int)far) != 0;
-      for (int p = 0; p < TJ / 64; ++p) {
-        const int k = 64 * p + l;
-        const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
-        double fx = 0.0, fy = 0.0, fz = 0.0;
-        const double mown = valid ? mass[ip] : 0.0;
-        for (int q0 = 0; q0 < nw; q0 += 4) {
-          double qx[4], qy[4], qz[4], qm[4], qh[4];
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int ql = min(q0 + t, 63);
-            qx[t] = rl(xi, ql);
-            qy[t] = rl(yi, ql);
-            qz[t] = rl(zi, ql);
-            qm[t] = rl(mown, ql);
-            qh[t] = rl(hi, ql);
-          }
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const double dx = qx[t] - a.x, dy = qy[t] - a.y, dz = qz[t] - b.x;
+        // near block: the direct loops of sym_block_f64 (lane = i, then
+        // lane = j), results in the output layout
+        double tx = 0.0, ty = 0.0, tz = 0.0;
+        if (__builtin_amdgcn_readfirstlane((int)far)) {
+#pragma unroll 4
+          for (int k = 0; k < TJ; ++k) {
+            const double2 a = tile[3 * k], b = tile[3 * k + 1];
+            const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
             const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            double w = newton_w64<true>(r2, qm[t]);
-            if (!farw) {
-              const double h = c.x + qh[t];
-              if (r2 <= h * h) w = soft_w64(r2, h, qm[t]);
-            }
-            fx = fma(w, dx, fx);
-            fy = fma(w, dy, fy);
-            fz = fma(w, dz, fz);
+            const double w = newton_w64<true>(r2, b.y);
+            tx = fma(w, dx, tx);
+            ty = fma(w, dy, ty);
+            tz = fma(w, dz, tz);
+          }
+        } else {
+#pragma unroll 2
+          for (int k = 0; k < TJ; ++k) {
+            const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
+            const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            const double h = c.x + hi;
+            double w = newton_w64<true>(r2, b.y);
+            if (r2 <= h * h) w = soft_w64(r2, h, b.y);
+            tx = fma(w, dx, tx);
+            ty = fma(w, dy, ty);
+            tz = fma(w, dz, tz);
           }
         }
-        jb[3 * k] = fx;
-        jb[3 * k + 1] = fy;
-        jb[3 * k + 2] = fz;
-      }
-    }
-    // this thread's accumulator entry (j = jt + tid), read while the other
-    // waves finish
-    double acc6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (!first && jown) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) acc6[c] = jacc[(size_t)c * chunk + jl];
-    }
-    __syncthreads();
-
-    // tile's j-side: the four waves' sums in order, into the accumulator
-    if (jown) {
-      const int k = tid;
-      double f[3];
+        for (int r = 0; r < 4; ++r) {
+          const int src = 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
+          const double vx = __shfl(tx, src), vy = __shfl(ty, src), vz = __shfl(tz, src);
+          two_sum_add(sum[r], cmp[r],
+                      cc == 0 ? vx : (cc == 1 ? vy : (cc == 2 ? vz : 0.0)));
+        }
+        const bool farw = __builtin_amdgcn_readfirstlane((int)far) != 0;
+        for (int p = 0; p < TJ / 64; ++p) {
+          const int k = 64 * p + l;
+          const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
+          double fx = 0.0, fy = 0.0, fz = 0.0;
+          const double mown = valid ? mass[ip] : 0.0;
+          for (int q0 = 0; q0 < nw; q0 += 4) {
+            double qx[4], qy[4], qz[4], qm[4], qh[4];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        f[c] = ((jbuf[3 * k + c] + jbuf[3 * (TJ + k) + c]) +
-                jbuf[3 * (2 * TJ + k) + c]) + jbuf[3 * (3 * TJ + k) + c];
-      }
+            for (int t = 0; t < 4; ++t) {
+              const int ql = min(q0 + t, 63);
+              qx[t] = rl(xi, ql);
+              qy[t] = rl(yi, ql);
+              qz[t] = rl(zi, ql);
+              qm[t] = rl(mown, ql);
+              qh[t] = rl(hi, ql);
+            }
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (first) {
-          acc6[c] = f[c];
-          acc6[3 + c] = 0.0;
-        } else {
-          two_sum_add(acc6[c], acc6[3 + c], f[c]);
+            for (int t = 0; t < 4; ++t) {
+              const double dx = qx[t] - a.x, dy = qy[t] - a.y, dz = qz[t] - b.x;
+              const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+              double w = newton_w64<true>(r2, qm[t]);
+              if (!farw) {
+                const double h = c.x + qh[t];
+                if (r2 <= h * h) w = soft_w64(r2, h, qm[t]);
+              }
+              fx = fma(w, dx, fx);
+              fy = fma(w, dy, fy);
+              fz = fma(w, dz, fz);
+            }
+          }
+          jb[3 * k] = fx;
+          jb[3 * k + 1] = fy;
+          jb[3 * k + 2] = fz;
         }
       }
+      // this thread's accumulator entry (j = jt + tid), read while the other
+      // waves finish
+      double acc6[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      if (!first && jown) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) jacc[(size_t)c * chunk + jl] = acc6[c];
-    }
-  }
+        for (int c = 0; c < 6; ++c) acc6[c] = jacc[(size_t)c * chunk + jl];
+      }
+      __syncthreads();
 
-  // far i-side: add each quad's four j-quad blocks (row rotations), keep
-  // quad q = 4r + b in the lanes of block b, then S = D_c - u_{i,c} D_3
-  double part[4] = {0.0, 0.0, 0.0, 0.0};
+      // tile's j-side: the four waves' sums in order, into the accumulator
+      if (jown) {
+        const int k = tid;
+        double f[3];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    double v = acci[q];
-    v += row_ror<4>(v);
-    v += row_ror<8>(v);
-    if (((l >> 2) & 3) == (q & 3)) part[q >> 2] = v;
+        for (int c = 0; c < 3; ++c) {
+          f[c] = ((jbuf[3 * k + c] + jbuf[3 * (TJ + k) + c]) +
+                  jbuf[3 * (2 * TJ + k) + c]) + jbuf[3 * (3 * TJ + k) + c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (first) {
+            acc6[c] = f[c];
+            acc6[3 + c] = 0.0;
+          } else {
+            two_sum_add(acc6[c], acc6[3 + c], f[c]);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) jacc[(size_t)c * chunk + jl] = acc6[c];
+      }
+    }
+    fold_far();
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int id = wbase + 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
-    const double ui = cc < 3 ? Pc[min(id, last)] - ccb : 0.0;
-    const double f = fma(-ui, quad_bcast3(part[r]), part[r]);
-    two_sum_add(sum[r], cmp[r], cc < 3 ? f : 0.0);
     if (cc < 3 && id < iend) out[(size_t)cc * os + id - obase] = sum[r] + cmp[r];
   }
 }
