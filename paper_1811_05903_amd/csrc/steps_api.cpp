@@ -2014,6 +2014,25 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
       if (want) R.v = v;
     }
     if (!R.v) R.v = cands.front();
+    // without the autotuner only the default runs: size scratch for it alone
+    if (!(b->flags & STEPS_BATCH_AUTOTUNE)) cands.assign(1, R.v);
+  }
+  // a choice the autotuner made before for this precision class and list of
+  // member sizes on this context is reused without timing
+  uint64_t sizes_hash = 1469598103934665603ull;  // FNV-1a over the sizes
+  for (int a = 0; a < A; ++a) {
+    sizes_hash = (sizes_hash ^ (uint64_t)(soff[a + 1] - soff[a])) * 1099511628211ull;
+  }
+  const std::pair<int, uint64_t> tune_key{R.cls, sizes_hash};
+  int bcount = 0;
+  const steps::BatchVariant *btable = steps::batch_variants(&bcount);
+  if ((b->flags & STEPS_BATCH_AUTOTUNE) && cands.size() > 1) {
+    for (const auto &e : c->batch_tuned) {
+      if (e.first == tune_key) {
+        R.v = &btable[e.second];
+        cands.assign(1, R.v);
+      }
+    }
   }
 
   // device memory
@@ -2127,22 +2146,7 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
   BATCH_TRY(batch_resort(R), "ensemble sort");
 
   // first forces, optionally timing every candidate kernel (once per
-  // precision class and list of member sizes on this context)
-  uint64_t sizes_hash = 1469598103934665603ull;  // FNV-1a over the sizes
-  for (int a = 0; a < A; ++a) {
-    sizes_hash = (sizes_hash ^ (uint64_t)(soff[a + 1] - soff[a])) * 1099511628211ull;
-  }
-  const std::pair<int, uint64_t> tune_key{R.cls, sizes_hash};
-  int bcount = 0;
-  const steps::BatchVariant *btable = steps::batch_variants(&bcount);
-  if ((b->flags & STEPS_BATCH_AUTOTUNE) && cands.size() > 1) {
-    for (const auto &e : c->batch_tuned) {
-      if (e.first == tune_key) {
-        R.v = &btable[e.second];
-        cands.assign(1, R.v);
-      }
-    }
-  }
+  // precision class and list of member sizes on this context: see above)
   if ((b->flags & STEPS_BATCH_AUTOTUNE) && cands.size() > 1) {
     hipEvent_t t0 = nullptr, t1 = nullptr;
     BATCH_TRY(hipEventCreate(&t0), "hipEventCreate");
