@@ -260,13 +260,6 @@ __device__ __forceinline__ double mfma4(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-// v of lane `lane` (uniform) on every lane
-__device__ __forceinline__ double rl(double v, int lane) {
-  const unsigned long long b = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, lane);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), lane);
-  return __longlong_as_double(((unsigned long long)hi << 32) | lo);
-}
 // every lane of a quad (4 consecutive lanes) takes the quad's lane 3 (DPP
 // quad_perm [3, 3, 3, 3])
 __device__ __forceinline__ double quad_bcast3(double v) {
@@ -289,6 +282,65 @@ __device__ __forceinline__ double row_ror(double v) {
                                           0xF, 0xF, true);
   return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) |
                               (unsigned)lo);
+}
+
+// every lane takes the value of lane (l + 1) mod 64 (DPP wave_rol:1)
+__device__ __forceinline__ double wave_rol1(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, 0x134, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0x134, 0xF,
+                                          0xF, true);
+  return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) |
+                              (unsigned)lo);
+}
+
+// ---------------------------------------------------------------------------
+// A (wave, tile) block of the symmetric FP64 kernels off the matrix cores,
+// each pair once (the pair term is antisymmetric, Sec. 2.2 Eq. 8).  Lane l
+// holds i = wave base + l; the tile is taken in parts of 64 j, and in step t
+// of a part lane l pairs its i with j = (l + t) mod 64 of the part, read
+// from LDS, so no two lanes share a j within a step.  One weight w per pair
+// serves both sides: the i-side sums m_j w (x_j - x_i) stay in the lane; the
+// j-side sums m_i w (x_i - x_j) travel with their j, every lane taking its
+// right neighbour's sums after each step (the sums of the j it meets next).
+// After 64 steps lane l holds the sums of j = l of the part, stored to
+// jb[3 k + c] (k the tile index of the j).  Blocks whose pairs all lie
+// beyond their softening radius (farw) skip the softening test.  Lanes past
+// the end of the chunk carry zero mass.  Additions run in a fixed order.
+// ---------------------------------------------------------------------------
+template <int TJ>
+__device__ __forceinline__ void near_block_f64(const double2 *tile, double xi,
+                                               double yi, double zi, double hi,
+                                               double mi, bool farw, int l,
+                                               double &tx, double &ty,
+                                               double &tz, double *jb) {
+  tx = ty = tz = 0.0;
+  for (int p = 0; p < TJ / 64; ++p) {
+    double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll 2
+    for (int t = 0; t < 64; ++t) {
+      const int k = 64 * p + ((l + t) & 63);
+      const double2 a = tile[3 * k], b = tile[3 * k + 1];
+      const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
+      const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+      double w = newton_w64<true>(r2, 1.0);
+      if (!farw) {
+        const double h = tile[3 * k + 2].x + hi;
+        if (r2 <= h * h) w = soft_w64(r2, h, 1.0);
+      }
+      const double wi = b.y * w, wj = mi * w;
+      tx = fma(wi, dx, tx);
+      ty = fma(wi, dy, ty);
+      tz = fma(wi, dz, tz);
+      jx = wave_rol1(fma(-wj, dx, jx));
+      jy = wave_rol1(fma(-wj, dy, jy));
+      jz = wave_rol1(fma(-wj, dz, jz));
+    }
+    const int k = 64 * p + l;
+    jb[3 * k] = jx;
+    jb[3 * k + 1] = jy;
+    jb[3 * k + 2] = jz;
+  }
 }
 
 template <int TJ>
@@ -652,76 +704,17 @@ __device__ __forceinline__ void sym_block_f64(
         part[r] = fma(-ui, s3, d2acc[r]);
       }
     } else {
-      // i-side: lane = i, every j of the tile
-      double tx = 0.0, ty = 0.0, tz = 0.0;
-      if (__builtin_amdgcn_readfirstlane((int)far)) {
-#pragma unroll 4
-        for (int k = 0; k < TJ; ++k) {
-          const double2 a = tile[3 * k], b = tile[3 * k + 1];
-          const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
-          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-          const double w = newton_w64<true>(r2, b.y);
-          tx = fma(w, dx, tx);
-          ty = fma(w, dy, ty);
-          tz = fma(w, dz, tz);
-        }
-      } else {
-#pragma unroll 2
-        for (int k = 0; k < TJ; ++k) {
-          const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
-          const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
-          const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-          const double h = c.x + hi;
-          double w = newton_w64<true>(r2, b.y);
-          if (r2 <= h * h) w = soft_w64(r2, h, b.y);
-          tx = fma(w, dx, tx);
-          ty = fma(w, dy, ty);
-          tz = fma(w, dz, tz);
-        }
-      }
+      // near block: each pair once, lane = i; i-side sums moved into the
+      // matrix-core output layout
+      double tx, ty, tz;
+      near_block_f64<TJ>(tile, xi, yi, zi, hi, valid ? mass[ip] : 0.0,
+                         __builtin_amdgcn_readfirstlane((int)far) != 0, l, tx,
+                         ty, tz, jb);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int src = 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
         const double vx = __shfl(tx, src), vy = __shfl(ty, src), vz = __shfl(tz, src);
         part[r] = cc == 0 ? vx : (cc == 1 ? vy : (cc == 2 ? vz : 0.0));
-      }
-      // j-side: lane = j of the tile, every valid i of the wave, each read
-      // from its own lane (v_readlane), four per batch; lanes past nw carry
-      // zero mass
-      const bool farw = __builtin_amdgcn_readfirstlane((int)far) != 0;
-      for (int p = 0; p < TJ / 64; ++p) {
-        const int k = 64 * p + l;
-        const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
-        double fx = 0.0, fy = 0.0, fz = 0.0;
-        const double mown = valid ? mass[ip] : 0.0;
-        for (int q0 = 0; q0 < nw; q0 += 4) {
-          double qx[4], qy[4], qz[4], qm[4], qh[4];
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int ql = min(q0 + t, 63);
-            qx[t] = rl(xi, ql);
-            qy[t] = rl(yi, ql);
-            qz[t] = rl(zi, ql);
-            qm[t] = rl(mown, ql);
-            qh[t] = rl(hi, ql);
-          }
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const double dx = qx[t] - a.x, dy = qy[t] - a.y, dz = qz[t] - b.x;
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            double w = newton_w64<true>(r2, qm[t]);
-            if (!farw) {
-              const double h = c.x + qh[t];
-              if (r2 <= h * h) w = soft_w64(r2, h, qm[t]);
-            }
-            fx = fma(w, dx, fx);
-            fy = fma(w, dy, fy);
-            fz = fma(w, dz, fz);
-          }
-        }
-        jb[3 * k] = fx;
-        jb[3 * k + 1] = fy;
-        jb[3 * k + 2] = fz;
       }
     }
 #pragma unroll
@@ -966,75 +959,18 @@ __device__ __forceinline__ void sym_block_f64_q(
           if (cc < 3) jb[3 * (16 * G + jslot) + cc] = f;
         }
       } else {
-        // near block: the direct loops of sym_block_f64 (lane = i, then
-        // lane = j), results in the output layout
-        double tx = 0.0, ty = 0.0, tz = 0.0;
-        if (__builtin_amdgcn_readfirstlane((int)far)) {
-#pragma unroll 4
-          for (int k = 0; k < TJ; ++k) {
-            const double2 a = tile[3 * k], b = tile[3 * k + 1];
-            const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            const double w = newton_w64<true>(r2, b.y);
-            tx = fma(w, dx, tx);
-            ty = fma(w, dy, ty);
-            tz = fma(w, dz, tz);
-          }
-        } else {
-#pragma unroll 2
-          for (int k = 0; k < TJ; ++k) {
-            const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
-            const double dx = a.x - xi, dy = a.y - yi, dz = b.x - zi;
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            const double h = c.x + hi;
-            double w = newton_w64<true>(r2, b.y);
-            if (r2 <= h * h) w = soft_w64(r2, h, b.y);
-            tx = fma(w, dx, tx);
-            ty = fma(w, dy, ty);
-            tz = fma(w, dz, tz);
-          }
-        }
+        // near block: each pair once (lane = i), i-side results moved into
+        // the output layout
+        double tx, ty, tz;
+        near_block_f64<TJ>(tile, xi, yi, zi, hi, valid ? mass[ip] : 0.0,
+                           __builtin_amdgcn_readfirstlane((int)far) != 0, l,
+                           tx, ty, tz, jb);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int src = 16 * r + 4 * ((l >> 2) & 3) + (l >> 4);
           const double vx = __shfl(tx, src), vy = __shfl(ty, src), vz = __shfl(tz, src);
           two_sum_add(sum[r], cmp[r],
                       cc == 0 ? vx : (cc == 1 ? vy : (cc == 2 ? vz : 0.0)));
-        }
-        const bool farw = __builtin_amdgcn_readfirstlane((int)far) != 0;
-        for (int p = 0; p < TJ / 64; ++p) {
-          const int k = 64 * p + l;
-          const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
-          double fx = 0.0, fy = 0.0, fz = 0.0;
-          const double mown = valid ? mass[ip] : 0.0;
-          for (int q0 = 0; q0 < nw; q0 += 4) {
-            double qx[4], qy[4], qz[4], qm[4], qh[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              const int ql = min(q0 + t, 63);
-              qx[t] = rl(xi, ql);
-              qy[t] = rl(yi, ql);
-              qz[t] = rl(zi, ql);
-              qm[t] = rl(mown, ql);
-              qh[t] = rl(hi, ql);
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-              const double dx = qx[t] - a.x, dy = qy[t] - a.y, dz = qz[t] - b.x;
-              const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-              double w = newton_w64<true>(r2, qm[t]);
-              if (!farw) {
-                const double h = c.x + qh[t];
-                if (r2 <= h * h) w = soft_w64(r2, h, qm[t]);
-              }
-              fx = fma(w, dx, fx);
-              fy = fma(w, dy, fy);
-              fz = fma(w, dz, fz);
-            }
-          }
-          jb[3 * k] = fx;
-          jb[3 * k + 1] = fy;
-          jb[3 * k + 2] = fz;
         }
       }
       // this thread's accumulator entry (j = jt + tid), read while the other
