@@ -1448,39 +1448,56 @@ __device__ __forceinline__ void sym_block_mixed(
         }
       }
     } else if (live) {
-      for (int q = 0; q < TJ; q += 64) {
-        {
-          // softening tested per pair (coincident pairs take the softened
-          // branch, which gives 0)
+      // one part of 64 j per step; SOFT: softening tested per pair
+      // (coincident pairs take the softened branch, which gives 0)
+      auto part = [&](int q, auto soft_tag) {
+        constexpr bool SOFT = decltype(soft_tag)::value;
 #pragma unroll 2
-          for (int t = 0; t < 64; ++t) {
-            const int jj = q + ((l + t) & 63);
-            const float4 p = tpos[jj];
-            const float hj = tsoft[jj];
-            float jx = jw[jj], jy = jw[TJ + jj], jz = jw[2 * TJ + jj];
+        for (int t = 0; t < 64; ++t) {
+          const int jj = q + ((l + t) & 63);
+          const float4 p = tpos[jj];
+          const float hj = tsoft[jj];
+          float jx = jw[jj], jy = jw[TJ + jj], jz = jw[2 * TJ + jj];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-              const float dx = p.x - xi[r], dy = p.y - yi[r], dz = p.z - zi[r];
-              const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+          for (int r = 0; r < R; ++r) {
+            const float dx = p.x - xi[r], dy = p.y - yi[r], dz = p.z - zi[r];
+            const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+            const float y = __builtin_amdgcn_rsqf(r2);
+            const float y2 = y * y;
+            float w = y2 * y;
+            if (REFINE) w = fmaf(1.5f * fmaf(-r2, y2, 1.0f), w, w);
+            if (SOFT) {
               const float h = hj + hi[r];
-              const float y = __builtin_amdgcn_rsqf(r2);
-              const float y2 = y * y;
-              float w = y2 * y;
-              if (REFINE) w = fmaf(1.5f * fmaf(-r2, y2, 1.0f), w, w);
               if (r2 <= h * h) w = soft_w32(r2, h, 1.0f);
-              const float wi = p.w * w, wj = mi[r] * w;
-              tx[r] = fmaf(wi, dx, tx[r]);
-              ty[r] = fmaf(wi, dy, ty[r]);
-              tz[r] = fmaf(wi, dz, tz[r]);
-              jx = fmaf(wj, dx, jx);
-              jy = fmaf(wj, dy, jy);
-              jz = fmaf(wj, dz, jz);
             }
-            jw[jj] = jx;
-            jw[TJ + jj] = jy;
-            jw[2 * TJ + jj] = jz;
-            lds_step_fence();
+            const float wi = p.w * w, wj = mi[r] * w;
+            tx[r] = fmaf(wi, dx, tx[r]);
+            ty[r] = fmaf(wi, dy, ty[r]);
+            tz[r] = fmaf(wi, dz, tz[r]);
+            jx = fmaf(wj, dx, jx);
+            jy = fmaf(wj, dy, jy);
+            jz = fmaf(wj, dz, jz);
           }
+          jw[jj] = jx;
+          jw[TJ + jj] = jy;
+          jw[2 * TJ + jj] = jz;
+          lds_step_fence();
+        }
+      };
+      for (int q = 0; q < TJ; q += 64) {
+        // the tile failed the box test; a part whose every j lies beyond
+        // the largest combined softening from the wave's box skips the
+        // per-pair test (same margin as the tile test)
+        const float4 pj = tpos[q + l];
+        const double gx = fmax(0.0, fmax((double)pj.x - wb[3], wb[0] - (double)pj.x));
+        const double gy = fmax(0.0, fmax((double)pj.y - wb[4], wb[1] - (double)pj.y));
+        const double gz = fmax(0.0, fmax((double)pj.z - wb[5], wb[2] - (double)pj.z));
+        const double hs = (double)tsoft[q + l] + wb[6];
+        const bool jfar = gx * gx + gy * gy + gz * gz > fmax(hs * hs * (1.0 + 1e-6), 1e-30);
+        if (__builtin_amdgcn_ballot_w64(!jfar) == 0) {
+          part(q, std::false_type{});
+        } else {
+          part(q, std::true_type{});
         }
       }
     }
@@ -1567,7 +1584,7 @@ __device__ __forceinline__ void sym_block_mixed(
 // Symmetric mixed kernel: the unit grid of k_force_f64_sym; diagonal units
 // run the one-sided mixed block (same accumulation) into plane s.
 template <int R, bool KAHAN, bool REFINE>
-__global__ __launch_bounds__(kBlock) void k_force_mixed_sym(
+__global__ __launch_bounds__(kBlock, 4) void k_force_mixed_sym(
     const float *__restrict__ shadow, int n, int chunk, int nchunks,
     const double *__restrict__ tinfo, double *__restrict__ iplane,
     double *__restrict__ jacc) {
@@ -1683,7 +1700,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_force_mixed(
 // A diagonal unit (ibeg == jbeg) sums its chunk one-sided into the i-side.
 // Units are of nearly equal cost, so the grid is one workgroup per unit.
 template <int R, bool KAHAN>
-__global__ __launch_bounds__(kBlock) void k_batch_force_mixed_sym(
+__global__ __launch_bounds__(kBlock, 4) void k_batch_force_mixed_sym(
     const float *__restrict__ shadow, int stride, const int4 *__restrict__ units,
     const int *__restrict__ tbase, const int *__restrict__ uslot, int nunits,
     const double *__restrict__ tinfo, double *__restrict__ usum, int chunk) {
