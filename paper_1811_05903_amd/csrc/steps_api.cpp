@@ -239,10 +239,10 @@ int heuristic_jsplit(int cls, int64_t n, int r, int tj, int variant) {
 // Launch shape: a forced tile, else a shape tuned for (class, n), else the
 // heuristic, measured on MI355X at N = 2^15 ... 2^21:
 //   * FP64 from kSymMinN up: the symmetric matrix-core kernel (variant 14,
-//     15% ahead of the one-sided one at 2^18 and 23-25% at 2^20 and 2^21),
-//     from kSymQuadMinN in its j-quad layout (variant 30, a further 3% at
-//     2^19, 6.5% at 2^20 and 8% at 2^21), while its memory cap still allows
-//     kSymMinChunks chunks;
+//     15% ahead of the one-sided one at 2^18 and 23-25% at 2^20 and 2^21,
+//     1-2% ahead of variant 30 at 2^18), from kSymQuadMinN in its j-quad
+//     layout (variant 30, a further 2% at 2^19, 4.6% at 2^20 and 7% at
+//     2^21), while its memory cap still allows kSymMinChunks chunks;
 //   * mixed from kSymMinN up: the symmetric mixed kernel (variant 10),
 //     1.31x the one-sided one at 2^18 and 1.45x at 2^21 (FP64
 //     accumulation), under the same chunk cap;

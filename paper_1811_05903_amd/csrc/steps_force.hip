@@ -250,10 +250,10 @@ __device__ __forceinline__ void force_block_f64(
 // D (row m, column n), b the block.
 // ---------------------------------------------------------------------------
 constexpr double kSep = 6.0;
-// The symmetric kernel's near blocks run the direct loop on both sides, so
-// it sends more blocks to the matrix cores: with kSepSym = 12 the Gram
-// form's r^2 error stays below ~2 kSepSym^2 eps = 3.2e-14 relative (measured
-// 5% faster than 6 at N = 2^18, with unchanged errors against the oracle).
+// The symmetric kernels send more blocks to the matrix cores: with
+// kSepSym = 12 the Gram form's r^2 error stays below ~2 kSepSym^2 eps =
+// 3.2e-14 relative (measured 5% faster than 6 at N = 2^18, with unchanged
+// errors against the oracle).
 constexpr double kSepSym = 12.0;
 
 __device__ __forceinline__ double mfma4(double a, double b, double c) {
@@ -530,8 +530,8 @@ __device__ __forceinline__ void force_block_f64_mfma(
 //     row n of block b and j the row m; a product on v_mfma_f64_4x4x4_4b
 //     contracts over the high lane index, so the weights are transposed
 //     within each 4 x 4 block (lane permute) before the second product, and
-//     the four blocks' partials are added across lanes.  A near block runs
-//     the direct loop a second time with the roles swapped (lane = j).
+//     the four blocks' partials are added across lanes.  A near block
+//     takes each pair once in near_block_f64 (both sides from one weight).
 //     Each wave leaves its per-tile j sums in LDS; after the tile they are
 //     added in wave order and then into the unit's compensated accumulator
 //     (value, error) [6][C] in global memory, which only this workgroup
