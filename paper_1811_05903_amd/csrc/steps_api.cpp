@@ -1553,6 +1553,9 @@ constexpr int64_t kBatchTargetItems = 8192;
 // Chunk size of the symmetric ensemble kernels: the smallest of 1024,
 // 2048, ... whose unit slots (72 chunk bytes per unit, Q (Q + 1) / 2 units
 // for a member of Q chunks) fit in 8 GiB.
+// Steps per replay of the multi-step ensemble graph.
+constexpr int kBatchGraphSteps = 10;
+
 int batch_sym_chunk(const std::vector<int> &soff) {
   const double cap = 8.0 * (1ull << 30);
   int c = 1024;
@@ -1867,9 +1870,20 @@ int batch_member(const steps_cosmology *k, double a0, double a1, int nsteps,
   return STEPS_OK;
 }
 
-int batch_fail_cleanup(int rc, hipStream_t s, hipGraph_t g, hipGraphExec_t x) {
-  if (x) (void)hipGraphExecDestroy(x);
-  if (g) (void)hipGraphDestroy(g);
+// Captured step graphs of one ensemble run: [0] one step, [1] kBatchGraphSteps
+// steps in a row.
+struct BatchGraphs {
+  hipGraph_t g[2] = {nullptr, nullptr};
+  hipGraphExec_t x[2] = {nullptr, nullptr};
+};
+
+int batch_fail_cleanup(int rc, hipStream_t s, BatchGraphs &gr) {
+  for (int k = 0; k < 2; ++k) {
+    if (gr.x[k]) (void)hipGraphExecDestroy(gr.x[k]);
+    if (gr.g[k]) (void)hipGraphDestroy(gr.g[k]);
+    gr.x[k] = nullptr;
+    gr.g[k] = nullptr;
+  }
   if (s) {
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
@@ -2122,13 +2136,12 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
   e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
   R.s = s;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  BatchGraphs gr;
 #define BATCH_TRY(expr, what)                                              \
   do {                                                                     \
     hipError_t e_ = (expr);                                                \
     if (e_ != hipSuccess) {                                                \
-      return batch_fail_cleanup(hip_fail(e_, what), s, graph, exec);       \
+      return batch_fail_cleanup(hip_fail(e_, what), s, gr);                \
     }                                                                      \
   } while (0)
 
@@ -2180,27 +2193,41 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
   BATCH_TRY(batch_forces(R), "ensemble force");
   c->batch_tile = steps_tile{R.v->r, R.v->tj, R.planes, R.v->variant};
 
-  // steps
+  // steps; with graphs, runs of kBatchGraphSteps steps replay one graph
+  // that holds them all (the step counter and the scalar table live on the
+  // device, so consecutive steps capture as the same kernels), and the
+  // steps left before a re-sort or the end replay a one-step graph
   const bool use_graph = (b->flags & STEPS_BATCH_GRAPH) != 0;
-  for (int k = 0; k < nsteps; ++k) {
+  auto capture = [&](int which, int steps) -> hipError_t {
+    hipError_t e1 = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e1 != hipSuccess) return e1;
+    hipError_t ce = hipSuccess;
+    for (int k = 0; k < steps && ce == hipSuccess; ++k) ce = batch_step(R);
+    hipError_t ee = hipStreamEndCapture(s, &gr.g[which]);
+    if (ce != hipSuccess) return ce;
+    if (ee != hipSuccess) return ee;
+    return hipGraphInstantiate(&gr.x[which], gr.g[which], nullptr, nullptr, 0);
+  };
+  for (int k = 0; k < nsteps;) {
     if (b->resort_every > 0 && k > 0 && k % b->resort_every == 0) {
       BATCH_TRY(batch_resort(R), "ensemble sort");
     }
     if (!use_graph) {
       BATCH_TRY(batch_step(R), "ensemble step");
+      ++k;
       continue;
     }
-    if (!exec) {
-      BATCH_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal),
-                "hipStreamBeginCapture");
-      hipError_t ce = batch_step(R);
-      hipError_t ee = hipStreamEndCapture(s, &graph);
-      BATCH_TRY(ce, "ensemble step capture");
-      BATCH_TRY(ee, "hipStreamEndCapture");
-      BATCH_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0),
-                "hipGraphInstantiate");
+    // steps before the next re-sort or the end
+    int left = nsteps - k;
+    if (b->resort_every > 0) {
+      left = std::min(left, b->resort_every - k % b->resort_every);
     }
-    BATCH_TRY(hipGraphLaunch(exec, s), "hipGraphLaunch");
+    const int which = left >= kBatchGraphSteps ? 1 : 0;
+    if (!gr.x[which]) {
+      BATCH_TRY(capture(which, which ? kBatchGraphSteps : 1), "ensemble step capture");
+    }
+    BATCH_TRY(hipGraphLaunch(gr.x[which], s), "hipGraphLaunch");
+    k += which ? kBatchGraphSteps : 1;
   }
 
   // back to the caller's order and arrays
@@ -2209,7 +2236,7 @@ int steps_batch_run(steps_ctx *c, const steps_batch *b, int32_t *status) {
   BATCH_TRY(steps::launch_scatter_cols(d.acc, N, d.orig, N, b->acc, (int)Nc, 3, s), "scatter");
   BATCH_TRY(hipStreamSynchronize(s), "ensemble run");
 #undef BATCH_TRY
-  batch_fail_cleanup(STEPS_OK, s, graph, exec);
+  batch_fail_cleanup(STEPS_OK, s, gr);
   write_status();
   return STEPS_OK;
 }

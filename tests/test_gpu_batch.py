@@ -56,7 +56,7 @@ def _grid(a0, a1, n):
     return g
 
 
-def _run(st, members, flags, ctx=None, resort=0, cosmos=None):
+def _run(st, members, flags, ctx=None, resort=0, cosmos=None, nsteps=NSTEPS):
     import torch
     offs, pos, vel, mass, soft = _arena(members)
     p, v = dev(pos), dev(vel)
@@ -65,7 +65,7 @@ def _run(st, members, flags, ctx=None, resort=0, cosmos=None):
                     for m in members]
     status = st.steps_batch_run(p, v, dev(mass), dev(soft), acc, offs, cs,
                                 [m.a0 for m in members], [m.a1 for m in members],
-                                NSTEPS, flags=flags, resort_every=resort, ctx=ctx)
+                                nsteps, flags=flags, resort_every=resort, ctx=ctx)
     return status, host(p), host(v), host(acc), offs
 
 
@@ -104,6 +104,21 @@ def test_graph_replay_bitwise_equals_launches(st):
     c = _run(st, members, st.STEPS_BATCH_GRAPH)
     for x, y, z in zip(a[1:4], b[1:4], c[1:4]):
         assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+@pytest.mark.parametrize("nsteps,resort", [(25, 0), (23, 11), (12, 5)])
+def test_multistep_graph_bitwise_equals_launches(st, nsteps, resort):
+    # graphs of ten steps replayed where ten steps remain before a re-sort or
+    # the end, one-step graphs elsewhere: the same result as launching every
+    # step's kernels directly (25 = 10 + 10 + 5 x 1; 23 with re-sorts after
+    # steps 11 and 22: 10 + 1, 10 + 1, 1; 12 with re-sorts every 5 steps: no
+    # ten-step run fits)
+    members = _members()
+    a = _run(st, members, st.STEPS_BATCH_GRAPH, resort=resort, nsteps=nsteps)
+    b = _run(st, members, 0, resort=resort, nsteps=nsteps)
+    assert a[0] == [0] * len(members)
+    for x, y in zip(a[1:4], b[1:4]):
+        assert np.array_equal(x, y)
 
 
 def test_bad_member_skipped_others_run(st):
