@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--batch-only", action="store_true",
                     help="run only the batched 64-member ensemble (no "
                          "sequential comparison; for profiling its kernels)")
+    ap.add_argument("--periodic-only", action="store_true",
+                    help="run only the periodic-box leg (for profiling its "
+                         "kernels)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the single-thread oracle sample")
     ap.add_argument("--tile", default=None, metavar="R,TJ,JSPLIT,VARIANT",
@@ -266,8 +269,14 @@ def main():
         print(json.dumps(workload5(st, dev, args)), flush=True)
         return
     if args.batch_only:
-        print(json.dumps({"batch": batch_leg(st, dev, args.batch_steps,
-                                             sequential=False)}), flush=True)
+        out = {"batch": batch_leg(st, dev, args.batch_steps, sequential=False)}
+        copy_calibration(args.copy_calibration)
+        print(json.dumps(out), flush=True)
+        return
+    if args.periodic_only:
+        out = {"periodic": periodic_leg(st, dev)}
+        copy_calibration(args.copy_calibration)
+        print(json.dumps(out), flush=True)
         return
 
     ps = synth.config(args.workload)
@@ -327,16 +336,22 @@ def main():
     if not args.no_glass:
         out["glass"] = glass_leg(st, dev)
         out["periodic"] = periodic_leg(st, dev)
-    if args.copy_calibration:
-        nb = args.copy_calibration << 20
-        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy calibration: %d MiB read + %d MiB written" % (
-            args.copy_calibration, args.copy_calibration))
+    copy_calibration(args.copy_calibration)
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration(mib):
+    """One device copy of `mib` MiB (a kernel of known traffic, to scale HBM
+    byte counters), if mib > 0."""
+    import torch
+    if not mib:
+        return
+    src = torch.ones((mib << 20) // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy calibration: %d MiB read + %d MiB written" % (mib, mib))
 
 
 def config2_full(st, dev):
@@ -392,10 +407,17 @@ def profiled_traffic(precision, tile, workload):
     """HBM bytes per force launch from the committed rocprofv3 summary of
     this kernel and launch shape, or None if there is none or the kernel
     source has changed since it was taken."""
+    return profile_traffic(os.path.join(
+        ROOT, "profiles", "%s_r%d_tj%d_v%d_workload%d.md"
+        % (force_kernel_name(precision, tile), tile["r"], tile["tj"],
+           tile["variant"], workload)))
+
+
+def profile_traffic(path):
+    """traffic_bytes_per_launch of a committed rocprofv3 summary, or None if
+    there is none or the kernel's source file (named with its SHA-256 in the
+    summary) has changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "%s_r%d_tj%d_v%d_workload%d.md"
-                        % (force_kernel_name(precision, tile), tile["r"],
-                           tile["tj"], tile["variant"], workload))
     if not os.path.exists(path):
         return None
     traffic, ok = None, False
@@ -639,8 +661,12 @@ def glass_leg(st, dev, n=262144, radius=500.0):
 def periodic_leg(st, dev):
     """Periodic box (Eqs. 2 and 5): one pair-sum evaluation per image rule
     on uniform particles in a box of side 100 Mpc, FP64, kernel time by HIP
-    events.  The full rule sums every image within 2.6 L (about 74 image
-    terms per pair, 179 image tests)."""
+    events (mean of two launches).  The full rule sums every image within
+    2.6 L: for uniform particles the expected number of image terms per
+    pair is the volume of that sphere in units of L^3, 4/3 pi 2.6^3 = 73.6,
+    which prices its roofline (20 flop per image term); the nearest-image
+    rule has one term per pair."""
+    import math
     import numpy as np
     import torch
     out = {}
@@ -654,12 +680,32 @@ def periodic_leg(st, dev):
         acc = st.steps_forces(p, m, h, ctx=ctx)
         torch.cuda.synchronize()
         ctx.force_timing(reset=True)
-        st.steps_forces(p, m, h, acc=acc, ctx=ctx)
+        for _ in range(2):
+            st.steps_forces(p, m, h, acc=acc, ctx=ctx)
         ms, cnt = ctx.force_timing(reset=True)
         ctx.close()
         name = "nearest" if images == 1 else "all_images_2.6L"
-        out[name] = {"n": n, "kernel_ms": ms / cnt, "pairs_per_s": float(n) * n / (ms / cnt * 1e-3)}
-        log("periodic %s: n=%d, %.2f ms, %.3e pairs/s" % (name, n, ms / cnt, out[name]["pairs_per_s"]))
+        kern_ms = ms / cnt
+        terms = 1.0 if images == 1 else 4.0 / 3.0 * math.pi * 2.6 ** 3
+        achieved = FLOP_PER_PAIR * terms * float(n) * n / (kern_ms * 1e-3) / 1e12
+        kernel = "k_force_periodic<%d>" % images
+        out[name] = {
+            "n": n, "kernel_ms": kern_ms, "launches": cnt,
+            "pairs_per_s": float(n) * n / (kern_ms * 1e-3),
+            "image_terms_per_pair": terms,
+            "roofline": {
+                "bound": "alu", "pipe": "fp64", "achieved": achieved,
+                "peak": FP64_PEAK_TF, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TF,
+                "traffic": profile_traffic(os.path.join(
+                    ROOT, "profiles", "k_force_periodic_images%d_uniform_box_n%d.md"
+                    % (images, n))),
+                "kernel": kernel,
+                "flop_per_pair": FLOP_PER_PAIR,
+                "pair_convention": "N^2 ordered pairs per evaluation, times "
+                                   "the expected image terms per pair"}}
+        log("periodic %s: n=%d, %.2f ms, %.3e pairs/s, %.3f of peak"
+            % (name, n, kern_ms, out[name]["pairs_per_s"], achieved / FP64_PEAK_TF))
     return out
 
 

@@ -5,15 +5,18 @@
 //                     formula: a direct image sum, no Fourier-space part);
 //   images = nearest: the leading term only, the nearest image
 //                     (quasi-periodic).
-// A pair's displacement is first brought to its nearest image,
+// The plain rule brings a pair's displacement to its nearest image,
 // d <- d - L rint(d / L) per component (each |d_k| <= L/2); the images
 // within 2.6 L of such a d are among the 179 triplets n in [-3, 3]^3 whose
 // box [n - 1/2, n + 1/2]^3 (in units of L) comes within 2.6 of the origin,
 // listed at compile time below.  A particle's own images cancel in pairs
-// (n and -n) and are skipped.  FP64, over Morton-sorted particles with
-// per-block shortcuts that give the same bits as the per-pair rules (see
-// k_force_periodic); per-tile partials added into compensated running
-// totals, j-splits reduced in fixed order and scattered back.
+// (n and -n) and are skipped.  FP64, over Morton-sorted particles; blocks
+// of (128 i, 128 j) whose displacement ranges allow it take the shifts or
+// image lists once per block instead of per pair (see k_force_periodic);
+// per-tile partials added into compensated running totals, j-splits
+// reduced in fixed order and scattered back.
+
+#include <type_traits>
 
 #include "steps_internal.h"
 #include "steps_pair.h"
@@ -61,8 +64,22 @@ constexpr ImageTable make_images() {
 __constant__ ImageTable kImages = make_images();
 static_assert(make_images().count == 179, "image candidate list");
 
+// m r^-3 with the e^2 term of the correction to v_rsq_f64 (e = 1 - r^2 y^2,
+// r^-3 = y^3 (1 + 3/2 e + 15/8 e^2 + O(e^3))), written as
+// t (1 + 3/2 e (1 + 5/4 e)) with t = m y^3: each constant is an operand of
+// its own instruction, so none has to be rebuilt in a register per pair.
+// The image sums cancel heavily, so the periodic kernel keeps the e^2 term.
+__device__ __forceinline__ double newton_w64_e2(double r2, double m) {
+  const double y = __builtin_amdgcn_rsq(r2);
+  const double y2 = y * y;
+  const double e = fma(-r2, y2, 1.0);
+  const double t = (m * y) * y2;
+  const double q = e * fma(e, 1.25, 1.0);
+  return fma(t * q, 1.5, t);
+}
+
 __device__ __forceinline__ double pair_w(double r2, double h, double m) {
-  return r2 <= h * h ? soft_w64(r2, h, m) : newton_w64<true>(r2, m);
+  return r2 <= h * h ? soft_w64(r2, h, m) : newton_w64_e2(r2, m);
 }
 
 __device__ __forceinline__ double wave_lo(double v) {
@@ -82,13 +99,17 @@ __device__ __forceinline__ double wave_hi(double v) {
 // range over L sits strictly inside (k - 1/2, k + 1/2) for one integer k,
 // every pair's nearest image along the axis is the shift -k L (rounding is
 // monotone, so the per-pair rint(d / L) is k as well), and the block uses
-// it without the per-pair wrap -- the same operations on the same values,
-// so the same bits.  Such a block whose minimum-image boxes are farther
-// apart than the largest combined softening also skips the softening test.
-// With every image (IMAGES = 2), such a block loops only over the candidate
-// images whose shifted box comes within 2.6 L; the rest would fail the
-// per-pair cut for every pair (the box distance is formed with the same
-// operations as r^2, so it bounds it from below exactly).
+// it without the per-pair wrap (the same operations on the same values, so
+// the same bits).  Such a block whose minimum-image boxes are farther apart
+// than the largest combined softening also skips the softening test, and
+// applies the shift to its i positions once (x_j - (x_i + k L): rounded at
+// the scale of the positions, as the per-pair difference already is).
+// With every image (IMAGES = 2), a block takes its candidate images from
+// the raw displacement range instead (no wrap), image by image over the
+// whole tile: an image whose shifted box lies wholly inside 2.6 L and
+// beyond the softening needs no per-pair test, the others keep the cut and
+// softening tests; only blocks too wide for eight shifts per axis (particles
+// stored far outside the box) wrap each pair and test all 179 candidates.
 //
 // block (x, y) = (i-block of one wave, j-split); split y writes its
 // partial to out + y * 3n
@@ -145,10 +166,10 @@ __global__ __launch_bounds__(kWaveBlock) void k_force_periodic(
     __syncthreads();
 
     // the block's shift per axis, the wrapped displacement range [dl, dh]
-    // and the minimum-image gap
+    // and the minimum-image gap; the raw (unwrapped) range [rl, rh]
     const double *ti = tinfo + (size_t)(jt / kTJp) * 8;
     bool uniform = true;
-    double ks[3], dl[3], dh[3], g2 = 0.0;
+    double ks[3], dl[3], dh[3], rl[3], rh[3], g2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double dmn = ti[c] - wh[c], dmx = ti[3 + c] - wl[c];
@@ -156,6 +177,8 @@ __global__ __launch_bounds__(kWaveBlock) void k_force_periodic(
       const double kc = rint(fmn);
       uniform = uniform && fmn > kc - 0.5 && fmx < kc + 0.5;
       ks[c] = kc;
+      rl[c] = dmn;
+      rh[c] = dmx;
       dl[c] = fma(-L, kc, dmn);
       dh[c] = fma(-L, kc, dmx);
       const double g = fmax(0.0, fmax(dl[c], -dh[c]));
@@ -165,46 +188,138 @@ __global__ __launch_bounds__(kWaveBlock) void k_force_periodic(
     const bool uni = __builtin_amdgcn_readfirstlane((int)uniform) != 0;
     const bool far = uni && __builtin_amdgcn_readfirstlane(
                                 (int)(g2 > fmax(hs * hs * (1.0 + 1e-6), 1e-30))) != 0;
+    const int kend = min(kTJp, jend - jt);
 
-    // candidate images of a uniform block (every image): bit q of cm[q / 64]
-    unsigned long long cm[3] = {0ull, 0ull, 0ull};
-    if (IMAGES == 2 && uni) {
+    // Every image (IMAGES = 2) from the raw displacement range: the image
+    // shifts n that can bring a raw displacement of the block within 2.6 L
+    // lie in [floor((-2.6 L - rh) / L), ceil((2.6 L - rl) / L)] per axis (a
+    // superset: the rounding of the quotients is far below one unit).  With
+    // at most 8 per axis, lane t tests the shifts (lo_x + t % 8, lo_y + t / 8)
+    // for each lo_z + z, and ballots which boxes come within 2.6 L, which of
+    // those lie beyond the largest combined softening (no softening test)
+    // and which of these lie wholly inside 2.6 L (no per-pair test at
+    // all); the margins are far above the rounding of
+    // the per-pair terms.  Blocks holding a particle's own pair take the
+    // tested loop, which skips it (its images cancel in pairs).  Wider
+    // blocks (particles far outside the box) take the per-pair wrap below.
+    int nlo[3] = {0, 0, 0}, ncnt[3] = {0, 0, 0};
+    bool raw = IMAGES == 2;
+    if (IMAGES == 2) {
 #pragma unroll
-      for (int w = 0; w < 3; ++w) {
-        const int q = 64 * w + tid;
-        bool keep = false;
-        if (q < kImages.count) {
-          double gg[3];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const double nl = fma((double)kImages.n[q][c], L, dl[c]);
-            const double nh = fma((double)kImages.n[q][c], L, dh[c]);
-            gg[c] = fmax(0.0, fmax(nl, -nh));
-          }
-          keep = fma(gg[2], gg[2], fma(gg[1], gg[1], gg[0] * gg[0])) < cut2;
-        }
-        cm[w] = __ballot(keep);
+      for (int c = 0; c < 3; ++c) {
+        const double lo = floor((-2.6 * L - rh[c]) * invL);
+        const double hi = ceil((2.6 * L - rl[c]) * invL);
+        const bool ok = lo >= -1.0e6 && hi <= 1.0e6 && hi - lo < 8.0;  // NaN: false
+        raw = raw && ok;
+        nlo[c] = __builtin_amdgcn_readfirstlane(ok ? (int)lo : 0);
+        ncnt[c] = __builtin_amdgcn_readfirstlane(ok ? (int)(hi - lo) + 1 : 0);
       }
+      raw = __builtin_amdgcn_readfirstlane((int)raw) != 0;
     }
 
     double tx[kRp], ty[kRp], tz[kRp];
 #pragma unroll
     for (int r = 0; r < kRp; ++r) tx[r] = ty[r] = tz[r] = 0.0;
-    const int kend = min(kTJp, jend - jt);
     if (IMAGES == 1 && far) {
-      // one shift for the block, no softening, no coincident pairs
+      // one shift for the block, applied to the i side once: the image
+      // x_j - k L is at x_j - (x_i + k L); no softening, no coincident pairs
+      double qx[kRp], qy[kRp], qz[kRp];
+#pragma unroll
+      for (int r = 0; r < kRp; ++r) {
+        qx[r] = fma(ks[0], L, xi[r]);
+        qy[r] = fma(ks[1], L, yi[r]);
+        qz[r] = fma(ks[2], L, zi[r]);
+      }
       for (int k = 0; k < kend; ++k) {
         const double2 a = tile[3 * k], b = tile[3 * k + 1];
 #pragma unroll
         for (int r = 0; r < kRp; ++r) {
-          const double dx = fma(-L, ks[0], a.x - xi[r]);
-          const double dy = fma(-L, ks[1], a.y - yi[r]);
-          const double dz = fma(-L, ks[2], b.x - zi[r]);
+          const double dx = a.x - qx[r], dy = a.y - qy[r], dz = b.x - qz[r];
           const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-          const double w = newton_w64<true>(r2, b.y);
+          const double w = newton_w64_e2(r2, b.y);
           tx[r] = fma(w, dx, tx[r]);
           ty[r] = fma(w, dy, ty[r]);
           tz[r] = fma(w, dz, tz[r]);
+        }
+      }
+    } else if (IMAGES == 2 && raw) {
+      const int i0 = blockIdx.x * (kWaveBlock * kRp);
+      const bool own = jt < i0 + kWaveBlock * kRp && jt + kend > i0;
+      const int lx = tid & 7, ly = tid >> 3;
+      const double nx = (double)(nlo[0] + lx), ny = (double)(nlo[1] + ly);
+      const double ax0 = fma(nx, L, rl[0]), ax1 = fma(nx, L, rh[0]);
+      const double ay0 = fma(ny, L, rl[1]), ay1 = fma(ny, L, rh[1]);
+      const double gx = fmax(0.0, fmax(ax0, -ax1)), gy = fmax(0.0, fmax(ay0, -ay1));
+      const double fx = fmax(fabs(ax0), fabs(ax1)), fy = fmax(fabs(ay0), fabs(ay1));
+      const bool lane_ok = lx < ncnt[0] && ly < ncnt[1];
+      const double soft2 = fmax(hs * hs * (1.0 + 1e-6), 1e-30);
+      for (int z = 0; z < ncnt[2]; ++z) {
+        // this z-slice's images: within 2.6 L (keep); beyond the softening
+        // and not the own pair's block (sf); and wholly inside 2.6 L (in)
+        const double nz = (double)(nlo[2] + z);
+        const double az0 = fma(nz, L, rl[2]), az1 = fma(nz, L, rh[2]);
+        const double gz = fmax(0.0, fmax(az0, -az1)), fz = fmax(fabs(az0), fabs(az1));
+        const double gg = fma(gz, gz, fma(gy, gy, gx * gx));
+        const double ff = fma(fz, fz, fma(fy, fy, fx * fx));
+        const bool kp = lane_ok && gg < cut2 * (1.0 + 1e-9);
+        const bool sf = kp && !own && gg > soft2;
+        unsigned long long mk = __ballot(kp);
+        const unsigned long long msf = __ballot(sf);
+        const unsigned long long min_ = __ballot(sf && ff < cut2 * (1.0 - 1e-9));
+        while (mk) {
+          const int bit = __builtin_ctzll(mk);
+          mk &= mk - 1;
+          // image x_j + n L: displacement x_j - (x_i - n L)
+          const double sx = (double)(nlo[0] + (bit & 7));
+          const double sy = (double)(nlo[1] + (bit >> 3));
+          double qx[kRp], qy[kRp], qz[kRp];
+#pragma unroll
+          for (int r = 0; r < kRp; ++r) {
+            qx[r] = fma(-sx, L, xi[r]);
+            qy[r] = fma(-sy, L, yi[r]);
+            qz[r] = fma(-nz, L, zi[r]);
+          }
+          // no softening test; inside 2.6 L no cut test either (the lanes
+          // of a wave hold nearby i, so the cut mostly branches uniformly)
+          auto untested = [&](auto cut_tag) {
+            constexpr bool CUT = decltype(cut_tag)::value;
+#pragma unroll 2
+            for (int k = 0; k < kend; ++k) {
+              const double2 a = tile[3 * k], b = tile[3 * k + 1];
+#pragma unroll
+              for (int r = 0; r < kRp; ++r) {
+                const double ex = a.x - qx[r], ey = a.y - qy[r], ez = b.x - qz[r];
+                const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
+                if (!CUT || r2 < cut2) {
+                  const double w = newton_w64_e2(r2, b.y);
+                  tx[r] = fma(w, ex, tx[r]);
+                  ty[r] = fma(w, ey, ty[r]);
+                  tz[r] = fma(w, ez, tz[r]);
+                }
+              }
+            }
+          };
+          if ((min_ >> bit) & 1) {
+            untested(std::false_type{});
+          } else if ((msf >> bit) & 1) {
+            untested(std::true_type{});
+          } else {
+            for (int k = 0; k < kend; ++k) {
+              const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
+#pragma unroll
+              for (int r = 0; r < kRp; ++r) {
+                if (jt + k == ii[r]) continue;  // own images cancel in pairs
+                const double ex = a.x - qx[r], ey = a.y - qy[r], ez = b.x - qz[r];
+                const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
+                if (r2 < cut2) {
+                  const double w = pair_w(r2, c.x + hi[r], b.y);
+                  tx[r] = fma(w, ex, tx[r]);
+                  ty[r] = fma(w, ey, ty[r]);
+                  tz[r] = fma(w, ez, tz[r]);
+                }
+              }
+            }
+          }
         }
       }
     } else {
@@ -230,25 +345,6 @@ __global__ __launch_bounds__(kWaveBlock) void k_force_periodic(
             tx[r] = fma(w, dx, tx[r]);
             ty[r] = fma(w, dy, ty[r]);
             tz[r] = fma(w, dz, tz[r]);
-          } else if (uni) {
-#pragma unroll
-            for (int wd = 0; wd < 3; ++wd) {
-              unsigned long long mk = cm[wd];
-              while (mk) {
-                const int q = 64 * wd + __builtin_ctzll(mk);
-                mk &= mk - 1;
-                const double ex = fma((double)kImages.n[q][0], L, dx);
-                const double ey = fma((double)kImages.n[q][1], L, dy);
-                const double ez = fma((double)kImages.n[q][2], L, dz);
-                const double r2 = fma(ez, ez, fma(ey, ey, ex * ex));
-                if (r2 < cut2) {
-                  const double w = pair_w(r2, h, b.y);
-                  tx[r] = fma(w, ex, tx[r]);
-                  ty[r] = fma(w, ey, ty[r]);
-                  tz[r] = fma(w, ez, tz[r]);
-                }
-              }
-            }
           } else {
             for (int q = 0; q < kImages.count; ++q) {
               const double ex = fma((double)kImages.n[q][0], L, dx);

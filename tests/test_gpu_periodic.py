@@ -55,6 +55,47 @@ def test_periodic_forces_parity(st, images, n):
 
 
 @pytest.mark.parametrize("images", [1, 2])
+def test_periodic_far_outside_box(st, images):
+    # a third of the particles stored up to three box lengths outside: blocks
+    # whose raw displacement range is too wide for the per-block image list
+    # wrap each pair instead, next to blocks that take the list
+    n = 1100
+    pos, mass, soft = _box_set(n, 17)
+    rng = np.random.default_rng(18)
+    sel = rng.choice(n, n // 3, replace=False)
+    pos[:, sel] += L * rng.integers(-3, 4, (3, sel.size))
+    pos = np.ascontiguousarray(pos)
+    ref = oracle.forces_periodic(pos, mass, soft, L, images)
+    ctx = st.Context(0, precision="fp64")
+    ctx.set_periodic(L, images)
+    got = host(st.steps_forces(dev(pos), dev(mass), dev(soft), ctx=ctx))
+    ctx.close()
+    err = rel_err(got, ref)
+    print("far outside, images=%d: median %.2e max %.2e" % (images, np.median(err), err.max()))
+    assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("images,n,rows", [(1, 262144, 256), (2, 65536, 48)])
+def test_periodic_uniform_box_sampled_rows(st, images, n, rows):
+    # the timed periodic workload: uniform particles in a box of side 100,
+    # N and image rule as timed, on seeded-sampled rows
+    Lb = 100.0
+    rng = np.random.default_rng(40 + images)
+    pos = rng.uniform(0, Lb, (3, n))
+    mass, soft = rng.uniform(0.5, 2.0, n), np.full(n, 0.02 * Lb / n ** (1 / 3))
+    idx = np.sort(np.random.default_rng(900 + images).choice(n, rows, replace=False))
+    ref = oracle.forces_periodic(pos, mass, soft, Lb, images, idx=idx)
+    print("uniform box images=%d n=%d: %d oracle rows" % (images, n, rows), flush=True)
+    ctx = st.Context(0, precision="fp64")
+    ctx.set_periodic(Lb, images)
+    got = host(st.steps_forces(dev(pos), dev(mass), dev(soft), ctx=ctx))[:, idx]
+    ctx.close()
+    err = rel_err(got, ref)
+    print("uniform box images=%d: median %.2e max %.2e" % (images, np.median(err), err.max()))
+    assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("images", [1, 2])
 def test_periodic_lattice_is_force_free(st, images):
     k = 5
     g = (np.arange(k) + 0.5) * (L / k)
