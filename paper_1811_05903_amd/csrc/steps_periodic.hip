@@ -112,9 +112,11 @@ __device__ __forceinline__ double wave_hi(double v) {
 // stored far outside the box) wrap each pair and test all 179 candidates.
 //
 // block (x, y) = (i-block of one wave, j-split); split y writes its
-// partial to out + y * 3n
+// partial to out + y * 3n.  At most 128 VGPRs, four waves per SIMD (the
+// every-image kernel spills a few block-level values outside its pair
+// loops to get there).
 template <int IMAGES>
-__global__ __launch_bounds__(kWaveBlock) void k_force_periodic(
+__global__ __launch_bounds__(kWaveBlock, 4) void k_force_periodic(
     const double *__restrict__ pos, const double *__restrict__ mass,
     const double *__restrict__ soft, int n, int jchunk, double L,
     const double *__restrict__ tinfo, double *__restrict__ out) {
