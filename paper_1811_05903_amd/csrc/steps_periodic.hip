@@ -199,22 +199,22 @@ __global__ __launch_bounds__(kWaveBlock, 4) void k_force_periodic(
     // at most 8 per axis, lane t tests the shifts (lo_x + t % 8, lo_y + t / 8)
     // for each lo_z + z, and ballots which boxes come within 2.6 L, which of
     // those lie beyond the largest combined softening (no softening test)
-    // and which of these lie wholly inside 2.6 L (no per-pair test at
-    // all); the margins are far above the rounding of
-    // the per-pair terms.  Blocks holding a particle's own pair take the
-    // tested loop, which skips it (its images cancel in pairs).  Wider
-    // blocks (particles far outside the box) take the per-pair wrap below.
+    // and which of these lie wholly inside 2.6 L (no per-pair test at all);
+    // the margins are far above the rounding of the per-pair terms.  Blocks
+    // holding a particle's own pair take the tested loop, which skips it
+    // (its images cancel in pairs).  Wider blocks (particles far outside
+    // the box) take the per-pair wrap below.
     int nlo[3] = {0, 0, 0}, ncnt[3] = {0, 0, 0};
     bool raw = IMAGES == 2;
     if (IMAGES == 2) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double lo = floor((-2.6 * L - rh[c]) * invL);
-        const double hi = ceil((2.6 * L - rl[c]) * invL);
-        const bool ok = lo >= -1.0e6 && hi <= 1.0e6 && hi - lo < 8.0;  // NaN: false
+        const double sl = floor((-2.6 * L - rh[c]) * invL);
+        const double sh = ceil((2.6 * L - rl[c]) * invL);
+        const bool ok = sl >= -1.0e6 && sh <= 1.0e6 && sh - sl < 8.0;  // NaN: false
         raw = raw && ok;
-        nlo[c] = __builtin_amdgcn_readfirstlane(ok ? (int)lo : 0);
-        ncnt[c] = __builtin_amdgcn_readfirstlane(ok ? (int)(hi - lo) + 1 : 0);
+        nlo[c] = __builtin_amdgcn_readfirstlane(ok ? (int)sl : 0);
+        ncnt[c] = __builtin_amdgcn_readfirstlane(ok ? (int)(sh - sl) + 1 : 0);
       }
       raw = __builtin_amdgcn_readfirstlane((int)raw) != 0;
     }
@@ -256,8 +256,9 @@ __global__ __launch_bounds__(kWaveBlock, 4) void k_force_periodic(
       const bool lane_ok = lx < ncnt[0] && ly < ncnt[1];
       const double soft2 = fmax(hs * hs * (1.0 + 1e-6), 1e-30);
       for (int z = 0; z < ncnt[2]; ++z) {
-        // this z-slice's images: within 2.6 L (keep); beyond the softening
-        // and not the own pair's block (sf); and wholly inside 2.6 L (in)
+        // this z-slice's images: within 2.6 L (mk); of those, beyond the
+        // softening in a block without an own pair (msoft); of these, wholly
+        // inside 2.6 L (minside)
         const double nz = (double)(nlo[2] + z);
         const double az0 = fma(nz, L, rl[2]), az1 = fma(nz, L, rh[2]);
         const double gz = fmax(0.0, fmax(az0, -az1)), fz = fmax(fabs(az0), fabs(az1));
@@ -266,8 +267,8 @@ __global__ __launch_bounds__(kWaveBlock, 4) void k_force_periodic(
         const bool kp = lane_ok && gg < cut2 * (1.0 + 1e-9);
         const bool sf = kp && !own && gg > soft2;
         unsigned long long mk = __ballot(kp);
-        const unsigned long long msf = __ballot(sf);
-        const unsigned long long min_ = __ballot(sf && ff < cut2 * (1.0 - 1e-9));
+        const unsigned long long msoft = __ballot(sf);
+        const unsigned long long minside = __ballot(sf && ff < cut2 * (1.0 - 1e-9));
         while (mk) {
           const int bit = __builtin_ctzll(mk);
           mk &= mk - 1;
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(kWaveBlock, 4) void k_force_periodic(
           }
           // no softening test; inside 2.6 L no cut test either (the lanes
           // of a wave hold nearby i, so the cut mostly branches uniformly)
-          auto untested = [&](auto cut_tag) {
+          auto unsoftened = [&](auto cut_tag) {
             constexpr bool CUT = decltype(cut_tag)::value;
 #pragma unroll 2
             for (int k = 0; k < kend; ++k) {
@@ -301,10 +302,10 @@ __global__ __launch_bounds__(kWaveBlock, 4) void k_force_periodic(
               }
             }
           };
-          if ((min_ >> bit) & 1) {
-            untested(std::false_type{});
-          } else if ((msf >> bit) & 1) {
-            untested(std::true_type{});
+          if ((minside >> bit) & 1) {
+            unsoftened(std::false_type{});
+          } else if ((msoft >> bit) & 1) {
+            unsoftened(std::true_type{});
           } else {
             for (int k = 0; k < kend; ++k) {
               const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
