@@ -659,9 +659,9 @@ def glass_leg(st, dev, n=262144, radius=500.0):
 
 
 def periodic_leg(st, dev):
-    """Periodic box (Eqs. 2 and 5): one pair-sum evaluation per image rule
-    on uniform particles in a box of side 100 Mpc, FP64, kernel time by HIP
-    events (mean of two launches).  The full rule sums every image within
+    """Periodic box (Eqs. 2 and 5): pair-sum evaluations per image rule on
+    uniform particles in a box of side 100 Mpc, FP64, kernel time by HIP
+    events (mean of two launches after an untimed one).  The full rule sums every image within
     2.6 L: for uniform particles the expected number of image terms per
     pair is the volume of that sphere in units of L^3, 4/3 pi 2.6^3 = 73.6,
     which prices its roofline (20 flop per image term); the nearest-image
