@@ -169,27 +169,41 @@ __global__ __launch_bounds__(kWaveBlock, 4) void k_force_periodic(
 
     // the block's shift per axis, the wrapped displacement range [dl, dh]
     // and the minimum-image gap; the raw (unwrapped) range [rl, rh]
+    // Along an axis whose range straddles one half-box (rint of its ends k
+    // and k + 1) every pair takes shift k or k + 1, so the wrapped values
+    // lie in [lo - k L, L/2] or [-L/2, hi - (k + 1) L] (rounding is
+    // monotone): the gap is the nearer of the two.  wrap: bit c set when
+    // axis c needs the per-pair wrap.
     const double *ti = tinfo + (size_t)(jt / kTJp) * 8;
-    bool uniform = true;
+    int wrap = 0;
     double ks[3], dl[3], dh[3], rl[3], rh[3], g2 = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double dmn = ti[c] - wh[c], dmx = ti[3 + c] - wl[c];
       const double fmn = dmn * invL, fmx = dmx * invL;
-      const double kc = rint(fmn);
-      uniform = uniform && fmn > kc - 0.5 && fmx < kc + 0.5;
+      const double kc = rint(fmn), kh = rint(fmx);
+      const bool ua = fmn > kc - 0.5 && fmx < kc + 0.5;
+      wrap |= ua ? 0 : 1 << c;
       ks[c] = kc;
       rl[c] = dmn;
       rh[c] = dmx;
       dl[c] = fma(-L, kc, dmn);
       dh[c] = fma(-L, kc, dmx);
-      const double g = fmax(0.0, fmax(dl[c], -dh[c]));
+      double g = 0.0;
+      if (kh == kc) {
+        g = fmax(0.0, fmax(dl[c], -dh[c]));
+      } else if (kh == kc + 1.0) {
+        g = fmin(fmax(0.0, dl[c]), fmax(0.0, -fma(-L, kh, dmx)));
+      }
       g2 = fma(g, g, g2);
     }
     const double hs = ti[6] + whm;
-    const bool uni = __builtin_amdgcn_readfirstlane((int)uniform) != 0;
-    const bool far = uni && __builtin_amdgcn_readfirstlane(
-                                (int)(g2 > fmax(hs * hs * (1.0 + 1e-6), 1e-30))) != 0;
+    wrap = __builtin_amdgcn_readfirstlane(wrap);
+    const bool uni = wrap == 0;
+    // every pair of the block beyond the largest combined softening
+    const bool nosoft = __builtin_amdgcn_readfirstlane(
+                            (int)(g2 > fmax(hs * hs * (1.0 + 1e-6), 1e-30))) != 0;
+    const bool far = uni && nosoft;
     const int kend = min(kTJp, jend - jt);
 
     // Every image (IMAGES = 2) from the raw displacement range: the image
@@ -325,6 +339,50 @@ __global__ __launch_bounds__(kWaveBlock, 4) void k_force_periodic(
           }
         }
       }
+    } else if (IMAGES == 1) {
+      // the per-pair wrap only along the axes that need it (the others
+      // shift by k L: the same bits), and no softening test where every
+      // pair lies beyond the largest combined softening (such a block holds
+      // no coincident or own pair: its gap is positive)
+      auto nearest = [&](auto wx, auto wy, auto wz, auto soft_tag) {
+        constexpr bool WX = decltype(wx)::value, WY = decltype(wy)::value,
+                       WZ = decltype(wz)::value, SOFT = decltype(soft_tag)::value;
+        for (int k = 0; k < kend; ++k) {
+          const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
+#pragma unroll
+          for (int r = 0; r < kRp; ++r) {
+            if (SOFT && jt + k == ii[r]) continue;  // own images cancel in pairs
+            double dx = a.x - xi[r], dy = a.y - yi[r], dz = b.x - zi[r];
+            dx = fma(-L, WX ? rint(dx * invL) : ks[0], dx);
+            dy = fma(-L, WY ? rint(dy * invL) : ks[1], dy);
+            dz = fma(-L, WZ ? rint(dz * invL) : ks[2], dz);
+            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            const double w = SOFT ? pair_w(r2, c.x + hi[r], b.y) : newton_w64_e2(r2, b.y);
+            tx[r] = fma(w, dx, tx[r]);
+            ty[r] = fma(w, dy, ty[r]);
+            tz[r] = fma(w, dz, tz[r]);
+          }
+        }
+      };
+      using T = std::true_type;
+      using F = std::false_type;
+      auto by_soft = [&](auto wx, auto wy, auto wz) {
+        if (nosoft) {
+          nearest(wx, wy, wz, F{});
+        } else {
+          nearest(wx, wy, wz, T{});
+        }
+      };
+      switch (wrap) {
+        case 0: by_soft(F{}, F{}, F{}); break;
+        case 1: by_soft(T{}, F{}, F{}); break;
+        case 2: by_soft(F{}, T{}, F{}); break;
+        case 3: by_soft(T{}, T{}, F{}); break;
+        case 4: by_soft(F{}, F{}, T{}); break;
+        case 5: by_soft(T{}, F{}, T{}); break;
+        case 6: by_soft(F{}, T{}, T{}); break;
+        default: by_soft(T{}, T{}, T{}); break;
+      }
     } else {
       for (int k = 0; k < kend; ++k) {
         const double2 a = tile[3 * k], b = tile[3 * k + 1], c = tile[3 * k + 2];
@@ -342,13 +400,7 @@ __global__ __launch_bounds__(kWaveBlock, 4) void k_force_periodic(
             dz = fma(-L, rint(dz * invL), dz);
           }
           const double h = c.x + hi[r];
-          if (IMAGES == 1) {
-            const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            const double w = pair_w(r2, h, b.y);
-            tx[r] = fma(w, dx, tx[r]);
-            ty[r] = fma(w, dy, ty[r]);
-            tz[r] = fma(w, dz, tz[r]);
-          } else {
+          {
             for (int q = 0; q < kImages.count; ++q) {
               const double ex = fma((double)kImages.n[q][0], L, dx);
               const double ey = fma((double)kImages.n[q][1], L, dy);
