@@ -178,8 +178,9 @@ int steps_ctx_set_tile(steps_ctx *ctx, const steps_tile *tile);
  * A particle's own images cancel in pairs and are left out.  Positions may
  * lie anywhere (the sums depend on them modulo L) and are not wrapped.
  * FP64 only (STEPS_E_UNSUPPORTED in the mixed modes); no potential, energy,
- * autotune or ensemble (STEPS_E_UNSUPPORTED).  The full image sum costs
- * about 180 image tests and 74 pair terms per pair.  L finite and > 0. */
+ * autotune or ensemble (STEPS_E_UNSUPPORTED).  The full image sum has
+ * about 74 terms per pair (about 100 evaluated against the cut for
+ * uniformly spread particles).  L finite and > 0. */
 #define STEPS_IMAGES_NONE 0
 #define STEPS_IMAGES_NEAREST 1
 #define STEPS_IMAGES_ALL 2
