@@ -48,6 +48,7 @@ if ROOT not in sys.path:
 FP64_PEAK_TF = 78.6
 FP32_PEAK_TF = 157.3
 FLOP_PER_PAIR = 20
+NOMINAL_CLOCK_GHZ = 2.4
 METRIC = "pair interactions/s (ordered-pair equivalent, whole KDK step)"
 
 
@@ -177,7 +178,9 @@ def kdk_leg(st, dev, ps, grid, steps, warmup, precision, tile=None,
             "flop_per_pair": FLOP_PER_PAIR,
             "pair_convention": "N^2 ordered pairs per evaluation (ordered-pair "
                                "equivalent: the symmetric kernels evaluate "
-                               "N(N-1)/2 unordered pairs)"},
+                               "N(N-1)/2 unordered pairs)",
+            "counters": counter_roofline(profile_path(precision, t, workload),
+                                         achieved / peak)},
     }, (pos, vel, acc)
 
 
@@ -316,14 +319,14 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ps, timed, args.cpu_seconds)
     if not args.no_modes:
-        out["modes"] = mode_table(st, ps, rows, dev, reps=3)
+        out["modes"] = mode_table(st, ps, rows, dev, reps=3, workload=args.workload)
     if not args.no_extras and args.workload == 3:
         w2 = synth.config(2)
         leg2, _ = kdk_leg(st, dev, w2, w2.a_grid(), 20, 3, "fp64", None, 2)
         w2rows = None
         if not args.no_modes:
             w2rows, _ = oracle_rows(w2, 4096, seed=22)
-        leg2["modes"] = mode_table(st, w2, w2rows, dev, reps=3)
+        leg2["modes"] = mode_table(st, w2, w2rows, dev, reps=3, workload=2)
         out["workload2"] = leg2
     if not args.no_extras:
         out["config2_200"] = config2_full(st, dev)
@@ -403,14 +406,57 @@ def force_kernel_name(precision, tile):
     return "k_force_f64_mfma" if tile["variant"] & 4 else "k_force_f64"
 
 
+def profile_path(precision, tile, workload):
+    """The committed rocprofv3 summary of this kernel, launch shape and
+    workload (which may not exist)."""
+    return os.path.join(ROOT, "profiles", "%s_r%d_tj%d_v%d_workload%d.md"
+                        % (force_kernel_name(precision, tile), tile["r"],
+                           tile["tj"], tile["variant"], workload))
+
+
 def profiled_traffic(precision, tile, workload):
     """HBM bytes per force launch from the committed rocprofv3 summary of
     this kernel and launch shape, or None if there is none or the kernel
     source has changed since it was taken."""
-    return profile_traffic(os.path.join(
-        ROOT, "profiles", "%s_r%d_tj%d_v%d_workload%d.md"
-        % (force_kernel_name(precision, tile), tile["r"], tile["tj"],
-           tile["variant"], workload)))
+    return profile_traffic(profile_path(precision, tile, workload))
+
+
+def counter_roofline(path, frac):
+    """Counter-based figures of a committed rocprofv3 summary (None if there
+    is none or its kernel source has changed): the measured clock and the
+    fraction `frac` of the nominal-clock peak restated at it, the executed
+    flops per ordered pair and the counter-weighted fraction (executed flops
+    instead of the 20-flop convention), VALU busy, and the FP64 pipe busy
+    (FP64 kernels) or the VALU issue rate against single issue (FP32)."""
+    import re
+    if profile_traffic(path) is None:
+        return None
+    text = open(path).read()
+
+    def num(pattern):
+        m = re.search(pattern, text)
+        return float(m.group(1)) if m else None
+
+    out = {"source": "profiles/" + os.path.basename(path),
+           "kernel_ms_profiled": num(r"average kernel ([0-9.]+) ms here"),
+           "clock_ghz": num(r"clock GRBM_GUI_ACTIVE[^\n]*= ([0-9.]+) GHz"),
+           "valu_busy": num(r"VALU busy SQ_ACTIVE_INST_VALU[^\n]*= ([0-9.]+)"),
+           "executed_flop_per_pair": num(r"executed FP(?:64|32) flops per [^(\n]*"
+                                         r"\([^)]*\): ([0-9.]+)")}
+    busy = num(r"FP64 pipe busy ([0-9.]+)")
+    if busy is not None:
+        out["fp64_pipe_busy"] = busy
+    issue = num(r"VALU issue \(rsq at 4 slots\) ([0-9.]+)x")
+    if issue is not None:
+        out["valu_issue_vs_single"] = issue
+    if out["clock_ghz"]:
+        out["frac_at_measured_clock"] = frac * NOMINAL_CLOCK_GHZ / out["clock_ghz"]
+    if out["executed_flop_per_pair"]:
+        out["counter_weighted_frac"] = frac * out["executed_flop_per_pair"] / FLOP_PER_PAIR
+    out["note"] = ("clock, busy and executed-flop figures from the summary's "
+                   "own run; fractions restate this run's frac with them "
+                   "(peak at %.1f GHz nominal)" % NOMINAL_CLOCK_GHZ)
+    return out
 
 
 def profile_traffic(path):
@@ -689,6 +735,8 @@ def periodic_leg(st, dev):
         terms = 1.0 if images == 1 else 4.0 / 3.0 * math.pi * 2.6 ** 3
         achieved = FLOP_PER_PAIR * terms * float(n) * n / (kern_ms * 1e-3) / 1e12
         kernel = "k_force_periodic<%d>" % images
+        prof = os.path.join(ROOT, "profiles", "k_force_periodic_images%d_uniform_box_n%d.md"
+                            % (images, n))
         out[name] = {
             "n": n, "kernel_ms": kern_ms, "launches": cnt,
             "pairs_per_s": float(n) * n / (kern_ms * 1e-3),
@@ -697,9 +745,8 @@ def periodic_leg(st, dev):
                 "bound": "alu", "pipe": "fp64", "achieved": achieved,
                 "peak": FP64_PEAK_TF, "unit": "TFLOP/s",
                 "frac": achieved / FP64_PEAK_TF,
-                "traffic": profile_traffic(os.path.join(
-                    ROOT, "profiles", "k_force_periodic_images%d_uniform_box_n%d.md"
-                    % (images, n))),
+                "traffic": profile_traffic(prof),
+                "counters": counter_roofline(prof, achieved / FP64_PEAK_TF),
                 "kernel": kernel,
                 "flop_per_pair": FLOP_PER_PAIR,
                 "pair_convention": "N^2 ordered pairs per evaluation, times "
@@ -796,10 +843,11 @@ def binned_errors(err, kappa, radius, nbins=3):
     return out
 
 
-def _mode_entry(st, ps, rows, dev, reps, prec, tile=None):
+def _mode_entry(st, ps, rows, dev, reps, prec, tile=None, workload=None):
     """One row of the modes table: mean kernel time of `reps` launches after
-    one warm-up in precision prec (optionally a forced launch shape), and the
-    error against the oracle rows if given."""
+    one warm-up in precision prec (optionally a forced launch shape), the
+    error against the oracle rows if given, and (FP64 and mixed, with the
+    workload named) the counter figures of the kernel's committed profile."""
     import numpy as np
     import torch
     n = ps.n
@@ -821,6 +869,9 @@ def _mode_entry(st, ps, rows, dev, reps, prec, tile=None):
              "tflops_20": FLOP_PER_PAIR * rate / 1e12,
              "frac_peak": FLOP_PER_PAIR * rate / 1e12 / peak,
              "tile": ctx.get_tile(n)}
+    if workload is not None and prec in ("fp64", "mixed"):
+        entry["counters"] = counter_roofline(
+            profile_path(prec, entry["tile"], workload), entry["frac_peak"])
     if rows is not None:
         idx, ref, kap = rows
         got = acc.cpu().numpy()[:, idx]
@@ -833,7 +884,7 @@ def _mode_entry(st, ps, rows, dev, reps, prec, tile=None):
     return entry
 
 
-def mode_table(st, ps, rows, dev, reps=3, refine=True):
+def mode_table(st, ps, rows, dev, reps=3, refine=True, workload=None):
     """Force-kernel rate per precision mode at this N (mean of `reps` timed
     launches after one warm-up), and the error against the oracle rows if
     given; with refine, also the default mixed shape with one Newton step on
@@ -841,7 +892,7 @@ def mode_table(st, ps, rows, dev, reps=3, refine=True):
     n = ps.n
     res = {}
     for prec in ("fp64", "mixed", "kahan"):
-        entry = _mode_entry(st, ps, rows, dev, reps, prec)
+        entry = _mode_entry(st, ps, rows, dev, reps, prec, workload=workload)
         res[prec] = entry
         log("n=%d %s: %.2f ms, %.3e pairs/s%s" % (
             n, prec, entry["kernel_ms"], entry["pairs_per_s"],
@@ -852,7 +903,7 @@ def mode_table(st, ps, rows, dev, reps=3, refine=True):
         # the one-sided FP64 kernel on the vector ALU alone (variant 3, no
         # matrix cores) beside the default
         res["fp64_valu"] = _mode_entry(st, ps, rows, dev, reps, "fp64",
-                                       (4, 128, 0, 3))
+                                       (4, 128, 0, 3), workload=workload)
         log("n=%d fp64 vector-ALU kernel: %.2f ms, %.3e pairs/s, %.3f of peak"
             % (n, res["fp64_valu"]["kernel_ms"], res["fp64_valu"]["pairs_per_s"],
                res["fp64_valu"]["frac_peak"]))

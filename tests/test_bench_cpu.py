@@ -52,3 +52,21 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_counter_figures_of_committed_summaries():
+    # the headline kernels' summaries give the clock, the pipe or issue
+    # figure and the executed flops that the bench line restates
+    f64 = bench.counter_roofline(
+        bench.profile_path("fp64", {"r": 1, "tj": 256, "variant": 30}, 3), 0.75)
+    assert f64 is not None
+    assert 2.0 < f64["clock_ghz"] < 2.5
+    assert 0.0 < f64["fp64_pipe_busy"] <= 1.0
+    assert 0.0 < f64["executed_flop_per_pair"] < 40.0
+    assert abs(f64["frac_at_measured_clock"] - 0.75 * 2.4 / f64["clock_ghz"]) < 1e-12
+    mixed = bench.counter_roofline(
+        bench.profile_path("mixed", {"r": 4, "tj": 256, "variant": 10}, 3), 0.7)
+    assert mixed is not None and 1.0 < mixed["valu_issue_vs_single"] < 2.0
+    assert "fp64_pipe_busy" not in mixed
+    assert bench.counter_roofline(
+        bench.profile_path("fp64", {"r": 9, "tj": 256, "variant": 30}, 3), 0.7) is None
