@@ -374,6 +374,27 @@ def test_full_size_config3_sampled_all_modes(st):
             assert np.median(err) <= 1e-5
 
 
+def test_full_size_config5_sampled_all_modes(st):
+    # N = 2^22 (the largest workload), default launch shapes; oracle on 64
+    # sampled particles
+    ps = synth.config(5)
+    idx = np.random.default_rng(5).choice(ps.n, 64, replace=False)
+    ref = oracle.forces(ps.pos, ps.mass, ps.soft, idx=idx)
+    p, m, h = dev(ps.pos), dev(ps.mass), dev(ps.soft)
+    for prec in ("fp64", "mixed", "kahan"):
+        print("config5 %s" % prec, flush=True)
+        ctx = st.Context(0, precision=prec)
+        got = host(st.steps_forces(p, m, h, ctx=ctx))[:, idx]
+        tile = ctx.get_tile(ps.n)
+        ctx.close()
+        err = rel_err(got, ref)
+        _report("%s config5 sampled %s" % (prec, tile), err)
+        if prec == "fp64":
+            assert err.max() <= FP64_TOL
+        else:
+            assert np.median(err) <= 1e-5
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_pair_momentum_vanishes(st, prec):
     # Eq. 8's pair sum is antisymmetric (Newton's third law), so
