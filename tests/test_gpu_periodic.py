@@ -75,10 +75,12 @@ def test_periodic_far_outside_box(st, images):
     assert err.max() <= 1e-12
 
 
-@pytest.mark.parametrize("images,n,rows", [(1, 262144, 256), (2, 65536, 48)])
+@pytest.mark.parametrize("images,n,rows", [(1, 262144, 256), (2, 65536, 48),
+                                           (1, 262144 + 37, 64), (2, 65536 + 37, 32)])
 def test_periodic_uniform_box_sampled_rows(st, images, n, rows):
     # the timed periodic workload: uniform particles in a box of side 100,
-    # N and image rule as timed, on seeded-sampled rows
+    # N and image rule as timed (and with a ragged last tile), on
+    # seeded-sampled rows
     Lb = 100.0
     rng = np.random.default_rng(40 + images)
     pos = rng.uniform(0, Lb, (3, n))
